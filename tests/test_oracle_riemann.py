@@ -1,0 +1,140 @@
+"""Pins of the oracle's exact Euler Riemann solver by properties of the exact
+solution that do not use the pressure function: integral conservation of the
+self-similar solution, Galilean and scaling invariance, symmetry, the
+two-rarefaction closed form, the vacuum condition and guess independence."""
+import numpy as np
+import pytest
+
+import oracle
+
+G = 1.4
+
+
+def _cons(W):
+    r, u, p = W
+    return np.array([r, r * u, p / (G - 1) + 0.5 * r * u * u])
+
+
+def _flux(W):
+    r, u, p = W
+    E = p / (G - 1) + 0.5 * r * u * u
+    return np.array([r * u, r * u * u + p, u * (E + p)])
+
+
+def _sample(WL, WR, s):
+    """Solution at x/t = s, via the same solver in the frame moving with speed s."""
+    sl = np.array([WL[0], WL[1] - s, WL[2]])
+    sr = np.array([WR[0], WR[1] - s, WR[2]])
+    _, _, W0, _ = oracle.riemann(G, sl, sr)
+    return np.array([W0[0], W0[1] + s, W0[2]])
+
+
+CASES = [
+    ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),         # shock tube: rarefaction, contact, shock
+    ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),          # two rarefactions
+    ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01)),       # strong shock
+    ((5.99924, 19.5975, 460.894), (5.99242, -6.19633, 46.0950)),  # colliding shocks
+    ((1.0, 0.75, 1.0), (0.125, 0.0, 0.1)),        # sonic rarefaction
+    ((0.3, -1.2, 0.02), (2.0, 0.4, 30.0)),
+]
+
+
+@pytest.mark.parametrize("WL,WR", CASES)
+def test_integral_conservation(WL, WR):
+    """For the self-similar solution W(x/t) of the Riemann problem,
+    int_{-X}^{X} (Q(s) - Q0(s)) ds = F(W_L) - F(W_R) for X beyond all waves
+    (the integral form of the conservation law at t = 1).  A wrong star pressure,
+    velocity, shock density or fan profile breaks this identity."""
+    WL, WR = np.array(WL), np.array(WR)
+    cl, cr = np.sqrt(G * WL[2] / WL[0]), np.sqrt(G * WR[2] / WR[0])
+    X = 2.0 * (abs(WL[1]) + abs(WR[1]) + 3 * cl + 3 * cr) + 5.0
+    n = 100000
+    s = -X + (np.arange(n) + 0.5) * (2 * X / n)
+    Qs = np.array([_cons(_sample(WL, WR, si)) for si in s])
+    Q0 = np.where((s < 0)[:, None], _cons(WL)[None, :], _cons(WR)[None, :])
+    lhs = (Qs - Q0).sum(axis=0) * (2 * X / n)
+    rhs = _flux(WL) - _flux(WR)
+    scale = np.abs(_cons(WL)).max() + np.abs(_cons(WR)).max()
+    # midpoint sampling puts an error of at most |jump| * ds / 2 at each of the
+    # (at most three) discontinuities; a wrong star state is off by O(1)
+    ds = 2 * X / n
+    assert np.all(np.abs(lhs - rhs) < 1.5 * scale * ds), (lhs, rhs, ds)
+
+
+@pytest.mark.parametrize("WL,WR", CASES)
+def test_galilean_and_scaling_invariance(WL, WR):
+    WL, WR = np.array(WL), np.array(WR)
+    ps, us, _, _ = oracle.riemann(G, WL, WR)
+    a = 0.37
+    ps2, us2, _, _ = oracle.riemann(G, WL + [0, a, 0], WR + [0, a, 0])
+    assert abs(ps2 - ps) < 1e-11 * ps and abs(us2 - (us + a)) < 1e-11 * (1 + abs(us))
+    # (rho, u, p) -> (A rho, B u, A B^2 p) maps solutions to solutions
+    A, B = 3.1, 0.6
+    sc = np.array([A, B, A * B * B])
+    ps3, us3, _, _ = oracle.riemann(G, WL * sc, WR * sc)
+    assert abs(ps3 - A * B * B * ps) < 1e-11 * A * B * B * ps
+    assert abs(us3 - B * us) < 1e-11 * (1 + abs(B * us))
+
+
+def test_symmetric_data():
+    for W in ([1.0, 1.0, 1.0], [0.5, -2.0, 0.3], [2.0, 0.7, 5.0]):
+        WL = np.array(W)
+        WR = np.array([W[0], -W[1], W[2]])
+        ps, us, W0, _ = oracle.riemann(G, WL, WR)
+        assert abs(us) < 1e-13
+
+
+def test_identical_states_unchanged():
+    for W in ([1.0, 0.0, 1.0], [0.3, 1.7, 0.02], [4.0, -0.9, 100.0]):
+        W = np.array(W)
+        ps, us, W0, it = oracle.riemann(G, W, W)
+        assert ps == W[2] and us == W[1]
+        np.testing.assert_array_equal(W0, W)
+
+
+def test_two_rarefaction_closed_form():
+    """When both waves are rarefactions the Riemann invariants give
+    p* = [(cL + cR - (g-1)/2 (uR - uL)) / (cL pL^-z + cR pR^-z)]^(1/z), z = (g-1)/(2g)."""
+    rng = np.random.default_rng(7)
+    z = (G - 1) / (2 * G)
+    n_checked = 0
+    for _ in range(200):
+        WL = np.array([rng.uniform(0.1, 3), rng.uniform(-3, 0), rng.uniform(0.1, 3)])
+        WR = np.array([rng.uniform(0.1, 3), rng.uniform(0, 3), rng.uniform(0.1, 3)])
+        cl, cr = np.sqrt(G * WL[2] / WL[0]), np.sqrt(G * WR[2] / WR[0])
+        if 2 / (G - 1) * (cl + cr) <= WR[1] - WL[1]:
+            continue
+        pt = ((cl + cr - 0.5 * (G - 1) * (WR[1] - WL[1])) / (cl / WL[2] ** z + cr / WR[2] ** z)) ** (1 / z)
+        if pt > min(WL[2], WR[2]):
+            continue
+        ps, _, _, _ = oracle.riemann(G, WL, WR)
+        assert abs(ps - pt) < 1e-11 * pt
+        n_checked += 1
+    assert n_checked > 50
+
+
+def test_vacuum_detected():
+    rc, _, _ = oracle.riemann_rc(G, [1.0, -5.0, 0.4], [1.0, 5.0, 0.4])
+    assert rc == oracle.E_VACUUM
+
+
+def test_nonphysical_detected():
+    rc, _, _ = oracle.riemann_rc(G, [1.0, 0.0, -0.4], [1.0, 0.0, 0.4])
+    assert rc == oracle.E_NONPHYSICAL
+    rc, _, _ = oracle.riemann_rc(G, [np.nan, 0.0, 0.4], [1.0, 0.0, 0.4])
+    assert rc == oracle.E_NONPHYSICAL
+
+
+def test_newton_cap_reported():
+    rc, _, it = oracle.riemann_rc(G, [1.0, 0.0, 1000.0], [1.0, 0.0, 0.01], maxit=1)
+    assert rc == oracle.E_NEWTON
+
+
+@pytest.mark.parametrize("WL,WR", CASES)
+def test_guess_independence(WL, WR):
+    """f is increasing and concave, so Newton reaches the same root from any
+    positive start."""
+    ps0, _, _, _ = oracle.riemann(G, WL, WR)
+    for guess in (1e-3 * ps0, 0.5 * ps0, 2 * ps0, 30 * ps0):
+        ps, _, _, _ = oracle.riemann(G, WL, WR, guess=guess)
+        assert abs(ps - ps0) < 1e-12 * ps0

@@ -1,0 +1,256 @@
+"""Pins of the oracle's whole step: exactness on polynomial data, exact shift at
+Courant number 1, linear stability (the paper's Courant-1 claim, Sec. 4.1),
+conservation, the printed advection convergence table (Sec. 4.2.3), the
+observed Euler rates (Sec. 4.3.1), and reductions of Euler to advection."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_21911_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RNG = np.random.default_rng(99)
+
+
+def _load_table(name):
+    rows = np.loadtxt(os.path.join(HERE, "golden", name), comments="#")
+    return {(int(r[0]), int(r[1])): r[2:] for r in rows}
+
+
+# ------------------------------------------------------------- advection
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_advection_polynomial_data_exact(order):
+    """Reconstruction, evolution and GL flux integration are all exact for data
+    from a polynomial of degree <= m, so one step reproduces the exact solution
+    away from the periodic wrap (Sec. 3.1 + eq. eq_finite_volume)."""
+    m = order - 1
+    n = 24
+    coef = RNG.normal(size=m + 1)
+    dx, q, vl, vr = I.adv_polynomial(n, coef)
+    c = oracle.cfg(oracle.ADVECTION, order, cfl=0.7)
+    v = oracle.init_interfaces(c, vl, vr)
+    qn, vn, dt, _, _ = oracle.step(c, dx, q, v, 0.0, 10.0)
+    shifted = np.polynomial.polynomial.polyval(np.array([[0.0, -dt]]).T, 1)  # noqa: F841
+    # exact translated data: u0(x - dt)
+    c_sh = np.polynomial.polynomial.polycompanion  # noqa: F841
+    xs = np.poly1d(coef[::-1])
+    sh = np.poly1d([1.0, -dt])
+    coef_t = xs(sh).c[::-1]
+    _, qe, ve, _ = I.adv_polynomial(n, coef_t)
+    sl = slice(4, n - 4)
+    np.testing.assert_allclose(qn[0, sl], qe[0, sl], atol=1e-12)
+    np.testing.assert_allclose(vn[0, 4:n - 3], ve[0, 4:n - 3], atol=1e-12)
+
+
+@pytest.mark.parametrize("order", [3, 5])
+def test_advection_courant_one_exact_shift(order):
+    """At Courant number 1 degrees 2 and 4 shift the data by exactly one cell:
+    they interpolate both interface values, so the polynomial's integral over
+    the cell and its left-end value move one cell to the right."""
+    n = 32
+    c = oracle.cfg(oracle.ADVECTION, order, cfl=1.0)
+    q = RNG.normal(size=(1, n))
+    v = RNG.normal(size=(1, n + 1))
+    v[0, n] = v[0, 0]
+    qn, vn, dt, _, _ = oracle.step(c, 1.0 / n, q, v, 0.0, 10.0)
+    np.testing.assert_allclose(qn[0], np.roll(q[0], 1), atol=1e-13)
+    np.testing.assert_allclose(vn[0, 1:], v[0, :n], atol=1e-13)
+
+
+def _step_matrix(order, cfl, n=16):
+    """Matrix of one periodic advection step on the state (q_0..q_{n-1}, V_0..V_{n-1})."""
+    c = oracle.cfg(oracle.ADVECTION, order, cfl=cfl)
+    A = np.zeros((2 * n, 2 * n))
+    for j in range(2 * n):
+        q = np.zeros((1, n))
+        v = np.zeros((1, n + 1))
+        if j < n:
+            q[0, j] = 1.0
+        else:
+            v[0, j - n] = 1.0
+            if j == n:
+                v[0, n] = 1.0
+        qn, vn, _, _, _ = oracle.step(c, 1.0 / n, q, v, 0.0, 10.0)
+        A[:n, j] = qn[0]
+        A[n:, j] = vn[0, :n]
+    return A
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_von_neumann_stability(order):
+    """Sec. 4.1: FV + GRPrec is linearly stable up to Courant number 1 at every
+    order; beyond it the spectral radius exceeds one."""
+    for cfl in (0.1, 0.5, 0.9, 1.0):
+        rho = np.abs(np.linalg.eigvals(_step_matrix(order, cfl))).max()
+        # at Courant number 1 some unit-modulus eigenvalues are defective, which
+        # perturbs computed eigenvalues by ~sqrt(machine epsilon)
+        assert rho <= 1.0 + 1e-6, (cfl, rho)
+    rho = np.abs(np.linalg.eigvals(_step_matrix(order, 1.05))).max()
+    assert rho > 1.05, rho
+
+
+@pytest.mark.parametrize("system", [oracle.ADVECTION, oracle.EULER])
+def test_periodic_conservation(system):
+    n = 50
+    for order in (2, 3, 4):
+        if system == oracle.ADVECTION:
+            dx, q, vl, vr = I.adv_sin2pi(n)
+            q = q + 0.1 * RNG.normal(size=q.shape)
+        else:
+            dx, q, vl, vr = I.euler_density_wave(n)
+            q = q.copy()
+            q[0] *= 1 + 0.05 * RNG.normal(size=n)
+        c = oracle.cfg(system, order)
+        v = oracle.init_interfaces(c, vl, vr)
+        qn, vn, t, k, _ = oracle.run(c, dx, q, v, 0.0, 1.0, max_steps=20)
+        tot0 = q.sum(axis=1)
+        tot1 = qn.sum(axis=1)
+        assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(q).sum(axis=1)), (tot0, tot1)
+
+
+def test_paper_advection_table():
+    """Sec. 4.2.3 table (FV + GRPrec, sin^4, t_out = 4).  First-step interface
+    data are the exact point values of the initial condition (the paper does not
+    say); errors are unnormalised sums dx |e|.  Order 2 agrees to 3 %, orders
+    3-5 to 25 % at N = 256 (35 % at N = 128; the gap shrinks faster than the
+    error itself), and the observed rates to 0.2 (0.4 at order 5)."""
+    tab = _load_table("paper_advection_grprec.txt")
+    for order in (2, 3, 4, 5):
+        errs = {}
+        for n in (64, 128, 256):
+            dx, q, vl, vr = I.adv_sin4(n)
+            c = oracle.cfg(oracle.ADVECTION, order)
+            v = oracle.init_interfaces(c, vl, vr)
+            qn, _, t, _, _ = oracle.run(c, dx, q, v, 0.0, 4.0)
+            assert t == 4.0
+            e = qn[0] - I.adv_sin4_exact_avg(n, 4.0)
+            errs[n] = (np.abs(e).max(), (np.abs(e) * dx).sum())
+        for n in (128, 256) if order > 2 else (64, 128, 256):
+            tol = 0.03 if order == 2 else (0.25 if n == 256 else 0.35)
+            for k in (0, 1):
+                assert abs(errs[n][k] / tab[(order, n)][k] - 1) < tol, (order, n, k, errs[n][k])
+        for n0, n1 in ((64, 128), (128, 256)):
+            ours = np.log2(errs[n0][0] / errs[n1][0])
+            paper = np.log2(tab[(order, n0)][0] / tab[(order, n1)][0])
+            # order 5: the printed rates (5.3) exceed the design order; ours are 5.0
+            assert abs(ours - paper) < (0.2 if order < 5 else 0.4), (order, n0, ours, paper)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_advection_convergence_order(order):
+    """Config: u0 = sin(2 pi x) on [0,1], t_end = 1; order m+1 observed."""
+    e = []
+    for n in (32, 64):
+        dx, q, vl, vr = I.adv_sin2pi(n)
+        c = oracle.cfg(oracle.ADVECTION, order)
+        v = oracle.init_interfaces(c, vl, vr)
+        qn, _, _, _, _ = oracle.run(c, dx, q, v, 0.0, 1.0)
+        e.append(np.abs(qn[0] - I.adv_sin2pi_exact_avg(n, 1.0)).max())
+    assert np.log2(e[0] / e[1]) > order - 0.2
+
+
+def test_square_wave_bounded():
+    dx, q, vl, vr = I.adv_square(64)
+    for order in (2, 3, 4, 5):
+        c = oracle.cfg(oracle.ADVECTION, order)
+        v = oracle.init_interfaces(c, vl, vr)
+        qn, vn, t, _, _ = oracle.run(c, dx, q, v, 0.0, 1.0)
+        assert np.all(np.isfinite(qn)) and np.abs(qn).max() < 2.0
+        assert abs(qn.sum() - q.sum()) < 1e-12 * np.abs(q).sum()
+
+
+# ------------------------------------------------------------- Euler
+@pytest.mark.parametrize("bc", [oracle.PERIODIC, oracle.TRANSMISSIVE])
+def test_euler_constant_state(bc):
+    n = 20
+    W = (0.8, 0.3, 1.7)
+    Q = I.prim_to_cons(np.full(n, W[0]), W[1], W[2])
+    for order in (2, 3, 4):
+        c = oracle.cfg(oracle.EULER, order, bc=bc)
+        v = np.concatenate([Q, Q[:, :1]], axis=1)
+        qn, vn, _, _, _ = oracle.run(c, 1.0 / n, Q, v, 0.0, 1.0, max_steps=5)
+        # round-off only: rows of the differentiation matrix sum to ~1e-15, not 0
+        np.testing.assert_allclose(qn, Q, rtol=1e-12)
+        np.testing.assert_allclose(vn, v, rtol=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_euler_density_wave_equals_advection(order):
+    """With u and p constant, rho u and E are affine in rho, the interface
+    problems are pure contacts and the flux is u Q + const, so the Euler scheme
+    acting on rho is the advection scheme with lambda = u at the same dt."""
+    n = 30
+    dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
+    c = oracle.cfg(oracle.EULER, order)
+    v = oracle.init_interfaces(c, vl, vr)
+    S = oracle.smax(c, q)
+    qe, ve, dte, _, _ = oracle.step(c, dx, q, v, 0.0, 10.0)
+    ca = oracle.cfg(oracle.ADVECTION, order, cfl=0.9 * 1.0 / S, lam=1.0)
+    qa, va, dta, _, _ = oracle.step(ca, dx, q[:1].copy(), v[:1].copy(), 0.0, 10.0)
+    assert abs(dta - dte) < 1e-15
+    np.testing.assert_allclose(qe[0], qa[0], atol=1e-12)
+    np.testing.assert_allclose(ve[0], va[0], atol=1e-12)
+
+
+def test_paper_euler_rates():
+    """Sec. 4.3.1 table: the observed rates between N = 40, 80, 160 agree with
+    the printed ones to 0.3 (magnitudes are not compared: the printed L1/Linf
+    ratio does not fit the stated unit domain)."""
+    tab = _load_table("paper_euler_grprec.txt")
+    for order in (2, 3, 4):
+        errs = {}
+        for n in (40, 80, 160):
+            dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=2.0)
+            c = oracle.cfg(oracle.EULER, order)
+            v = oracle.init_interfaces(c, vl, vr)
+            qn, _, t, _, _ = oracle.run(c, dx, q, v, 0.0, 4.0)
+            errs[n] = np.abs(qn[0] - I.euler_density_wave_exact_rho(n, 4.0)).max()
+        for n0, n1 in ((40, 80), (80, 160)):
+            ours = np.log2(errs[n0] / errs[n1])
+            paper = np.log2(tab[(order, n0)][0] / tab[(order, n1)][0])
+            assert abs(ours - paper) < 0.3, (order, n0, ours, paper)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_euler_nonlinear_smooth_self_convergence(order):
+    """A smooth acoustic pulse (u and p vary, so the flux is genuinely
+    nonlinear): differences between successive meshes fall at rate ~ m+1."""
+    def run(n):
+        dx, xf = I.grid(n)
+        xs = []
+        # cell averages by 8-point Gauss on each cell (smooth data)
+        gx, gw = np.polynomial.legendre.leggauss(8)
+        xq = 0.5 * (xf[:-1, None] + xf[1:, None]) + 0.5 * dx * gx[None, :]
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * xq)
+        u = 0.3 * np.sin(2 * np.pi * xq)
+        p = 1.0 + 0.28 * np.sin(2 * np.pi * xq)
+        Q = I.prim_to_cons(rho, u, p)
+        q = (Q * (0.5 * gw)[None, None, :]).sum(axis=2)
+        rf = 1.0 + 0.2 * np.sin(2 * np.pi * xf)
+        uf = 0.3 * np.sin(2 * np.pi * xf)
+        pf = 1.0 + 0.28 * np.sin(2 * np.pi * xf)
+        v = I.prim_to_cons(rf, uf, pf)
+        c = oracle.cfg(oracle.EULER, order)
+        qn, _, t, _, _ = oracle.run(c, dx, q, v, 0.0, 0.2)
+        del xs
+        return qn[0]
+    r = [run(n) for n in (32, 64, 128)]
+    coarsen = lambda a: 0.5 * (a[0::2] + a[1::2])
+    d1 = np.abs(coarsen(r[1]) - r[0]).max()
+    d2 = np.abs(coarsen(r[2]) - r[1]).max()
+    assert np.log2(d1 / d2) > order - 0.4, (d1, d2)
+
+
+def test_sod_with_linear_grprec_fails_at_first_step():
+    """Reading: the paper runs shock tubes only with GRPrecNL.  Linear GRPrec
+    (Godunov's theorem) puts a negative nodal pressure in the cell next to the
+    Sod jump at the first step and the predictor does not converge."""
+    for order in (2, 3, 4):
+        dx, q, vl, vr = I.euler_shock_tube(100)
+        c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE)
+        v = oracle.init_interfaces(c, vl, vr)
+        with pytest.raises(oracle.OracleError) as ei:
+            oracle.step(c, dx, q, v, 0.0, 0.2)
+        assert ei.value.code in (oracle.E_PREDICTOR, oracle.E_NONPHYSICAL)
