@@ -595,9 +595,10 @@ int orc_predictor_matrices(int m, double *g, double *w, double *D, double *Kinv_
 /* One time step of one domain (segment), eqs. (dt-FV) and (eq_finite_volume).
  * q:  [nv][n] cell averages at t^n;  v: [nv][n+1] interface states from the
  * previous step (index k is x_{k-1/2}; for periodic domains v[0] and v[n] are
- * the same interface).  Ghosts: periodic wrap, or transmissive copy of the end
- * cell average (needed by degree >= 3); at a transmissive boundary the outside
- * trace mirrors the inside trace, so the interface state is the inside trace. */
+ * the same interface).  Ghosts: periodic wrap, or, at a transmissive end, a
+ * ghost cell holding the end cell's average (zero-gradient extrapolation): it
+ * enters the degree >= 3 reconstructions as a neighbour average and the
+ * boundary Riemann problems as constant data. */
 
 double orc_smax(const orc_cfg *cf, int n, const double *q) {
   if (cf->system == 0) return fabs(cf->lambda);
@@ -686,6 +687,18 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
     orc_traces(cf, &s, qh, TL + (size_t)ntr * i, TR + (size_t)ntr * i);
   }
 
+  /* Transmissive ends: a ghost cell outside each end holds the end cell's
+   * average as constant data (zero-gradient extrapolation); a constant state
+   * is its own space-time evolution, so its trace is that average at every
+   * time. */
+  double *GL = (double *)malloc(sizeof(double) * ntr);
+  double *GR = (double *)malloc(sizeof(double) * ntr);
+  for (int vv = 0; vv < nv; ++vv)
+    for (int b = 0; b <= nn; ++b) {
+      GL[vv * (nn + 1) + b] = q[vv * n + 0];
+      GR[vv * (nn + 1) + b] = q[vv * n + n - 1];
+    }
+
   /* interfaces k = 0..n; interface k lies between cells k-1 and k */
   for (int k = 0; k <= n && rc == ORC_OK; ++k) {
     const double *tl, *tr; /* right trace of left cell, left trace of right cell */
@@ -694,9 +707,11 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
       tl = TR + (size_t)ntr * cl;
       tr = TL + (size_t)ntr * cr;
     } else if (k == 0) {
-      tl = tr = TL; /* mirror of cell 0's left trace */
+      tl = GL;
+      tr = TL;
     } else if (k == n) {
-      tl = tr = TR + (size_t)ntr * (n - 1);
+      tl = TR + (size_t)ntr * (n - 1);
+      tr = GR;
     } else {
       tl = TR + (size_t)ntr * (k - 1);
       tr = TL + (size_t)ntr * k;
@@ -732,6 +747,8 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
   free(TL);
   free(TR);
   free(Fb);
+  free(GL);
+  free(GR);
   if (dt_out) *dt_out = dt;
   if (t_out) *t_out = tn;
   return rc;

@@ -254,3 +254,34 @@ def test_sod_with_linear_grprec_fails_at_first_step():
         with pytest.raises(oracle.OracleError) as ei:
             oracle.step(c, dx, q, v, 0.0, 0.2)
         assert ei.value.code in (oracle.E_PREDICTOR, oracle.E_NONPHYSICAL)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_transmissive_ends_are_stable(order):
+    """Reading of 'transmissive': a ghost cell holding the end cell's average as
+    constant data.  Short domains stay physical and bounded for 1000 steps
+    (extrapolating the end cell's own polynomial instead is unstable)."""
+    for n in (3, 5, 12):
+        dx, q, vl, vr = I.euler_density_wave(n, amp=0.1, u=0.5, p=1.0)
+        c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE)
+        v = oracle.init_interfaces(c, vl, vr)
+        qn, _, _, k, _ = oracle.run(c, dx, q, v, 0.0, 1e9, 1000)
+        assert k == 1000
+        assert np.abs(qn[0] - 1.0).max() <= 0.1 + 1e-12
+        assert np.abs(qn[1] / qn[0] - 0.5).max() < 1e-10
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_transmissive_outflow_advection(order):
+    """A smooth bump carried out of a transmissive domain leaves it (nearly)
+    empty; the inflow ghost keeps the upstream value."""
+    n = 64
+    dx, xf = I.grid(n)
+    bump = lambda x: np.where(np.abs(x - 0.5) < 0.25, np.cos(2 * np.pi * (x - 0.5)) ** 4, 0.0)
+    gx, gw = np.polynomial.legendre.leggauss(10)
+    xq = 0.5 * (xf[:-1, None] + xf[1:, None]) + 0.5 * dx * gx[None, :]
+    q = (bump(xq) * 0.5 * gw).sum(axis=1)[None, :]
+    v = bump(xf)[None, :]
+    c = oracle.cfg(oracle.ADVECTION, order, bc=oracle.TRANSMISSIVE)
+    qn, _, _, _, _ = oracle.run(c, dx, q, v.copy(), 0.0, 1.0)
+    assert np.abs(qn).max() < 1e-3
