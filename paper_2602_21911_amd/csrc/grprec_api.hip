@@ -1,0 +1,873 @@
+// grprec_api.hip -- host side of libgrprec.so: validation, plans, tile lists,
+// graph capture, autotuning and the C ABI declared in include/grprec.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "../../include/grprec.h"
+#include "grprec_internal.h"
+
+namespace grp {
+// kernels.hip
+template <int M> hipError_t launch_euler(const EulerArgs<M> &, int, int, hipStream_t);
+template <int M> hipError_t euler_occupancy(int, int *);
+template <int M> hipError_t launch_adv(const AdvArgs<M> &, int, hipStream_t);
+hipError_t launch_init_interfaces_euler(double *, const double *, int, const Gas &, int, double, Ctl *,
+                                        hipStream_t);
+hipError_t launch_init_interfaces_adv(double *, const double *, int, double, hipStream_t);
+hipError_t launch_domain_smax(const double *, int, const Seg &, int, const Gas &, Ctl *, hipStream_t);
+hipError_t launch_reset_ctl(Ctl *, const Seg &, double, long long, int, double, hipStream_t);
+hipError_t launch_run_prologue(Ctl *, const Seg &, int, double, hipStream_t);
+hipError_t launch_digest(const double *, long long, Ctl *, hipStream_t);
+
+// ------------------------------------------------------------ quadrature
+// Gauss-Legendre nodes and weights on [0,1] from their closed forms (n <= 5).
+static void gl_nodes(int n, double *x, double *w) {
+  std::vector<double> xs, ws;  // on [-1,1], ascending
+  switch (n) {
+    case 1: xs = {0.0}; ws = {2.0}; break;
+    case 2: {
+      double a = 1.0 / std::sqrt(3.0);
+      xs = {-a, a}; ws = {1.0, 1.0};
+      break;
+    }
+    case 3: {
+      double a = std::sqrt(0.6);
+      xs = {-a, 0.0, a}; ws = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+      break;
+    }
+    case 4: {
+      double r = 2.0 / 7.0 * std::sqrt(6.0 / 5.0);
+      double xi = std::sqrt(3.0 / 7.0 - r), xo = std::sqrt(3.0 / 7.0 + r);
+      double wi = (18.0 + std::sqrt(30.0)) / 36.0, wo = (18.0 - std::sqrt(30.0)) / 36.0;
+      xs = {-xo, -xi, xi, xo}; ws = {wo, wi, wi, wo};
+      break;
+    }
+    default: {
+      double r = 2.0 * std::sqrt(10.0 / 7.0);
+      double xi = std::sqrt(5.0 - r) / 3.0, xo = std::sqrt(5.0 + r) / 3.0;
+      double wi = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0, wo = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+      xs = {-xo, -xi, 0.0, xi, xo}; ws = {wo, wi, 128.0 / 225.0, wi, wo};
+      break;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    x[k] = 0.5 * (xs[k] + 1.0);
+    w[k] = 0.5 * ws[k];
+  }
+}
+
+// Lagrange polynomial l_k on nodes g (value, derivative) at t.
+static double lag(int n, const double *g, int k, double t) {
+  double v = 1.0;
+  for (int j = 0; j < n; ++j)
+    if (j != k) v *= (t - g[j]) / (g[k] - g[j]);
+  return v;
+}
+static double lag_d(int n, const double *g, int k, double t) {
+  // derivative by the product rule: sum over the dropped factor
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (j == k) continue;
+    double prod = 1.0 / (g[k] - g[j]);
+    for (int l = 0; l < n; ++l)
+      if (l != k && l != j) prod *= (t - g[l]) / (g[k] - g[l]);
+    s += prod;
+  }
+  return s;
+}
+
+// Space-time predictor constants for degree M: the time matrix
+// K[b][l] = l_b(1) l_l(1) - int_0^1 l_b' l_l (Gauss-Legendre at the nodes is
+// exact for it: = l_b(1) l_l(1) - w_l l_b'(g_l)), inverted by Gauss-Jordan.
+template <int M>
+static bool st_constants(StConst<M> &C) {
+  constexpr int n = M + 1;
+  double g[5], w[5];
+  gl_nodes(n, g, w);
+  double K[n][2 * n];
+  for (int b = 0; b < n; ++b) {
+    for (int l = 0; l < n; ++l) {
+      K[b][l] = lag(n, g, b, 1.0) * lag(n, g, l, 1.0) - w[l] * lag_d(n, g, b, g[l]);
+      K[b][n + l] = (b == l) ? 1.0 : 0.0;
+    }
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(K[r][col]) > std::fabs(K[piv][col])) piv = r;
+    if (std::fabs(K[piv][col]) < 1e-300) return false;
+    for (int k = 0; k < 2 * n; ++k) std::swap(K[col][k], K[piv][k]);
+    double d = K[col][col];
+    for (int k = 0; k < 2 * n; ++k) K[col][k] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      double f = K[r][col];
+      for (int k = 0; k < 2 * n; ++k) K[r][k] -= f * K[col][k];
+    }
+  }
+  for (int b = 0; b < n; ++b)
+    for (int l = 0; l < n; ++l) C.KW[b][l] = K[b][n + l] * w[l];
+  for (int a = 0; a < n; ++a) {
+    for (int k = 0; k < n; ++k) C.D[a][k] = lag_d(n, g, k, g[a]);
+    C.l0[a] = lag(n, g, a, 0.0);
+    C.l1[a] = lag(n, g, a, 1.0);
+    C.w[a] = w[a];
+    double xi = g[a] - 0.5, x2 = xi * xi;
+    C.phi[a][0] = xi;
+    C.phi[a][1] = x2 - 1.0 / 12.0;
+    C.phi[a][2] = x2 * xi;
+    C.phi[a][3] = x2 * x2 - 1.0 / 80.0;
+  }
+  return true;
+}
+
+static Gas make_gas(double g) {
+  Gas G;
+  G.g = g;
+  G.gm1 = g - 1.0;
+  G.gp1 = g + 1.0;
+  G.z = (g - 1.0) / (2.0 * g);
+  G.inv_g = 1.0 / g;
+  G.two_gm1 = 2.0 / (g - 1.0);
+  G.two_gp1 = 2.0 / (g + 1.0);
+  G.gm1_gp1 = (g - 1.0) / (g + 1.0);
+  G.twog_gm1 = 2.0 * g / (g - 1.0);
+  G.gp1_2g = (g + 1.0) / (2.0 * g);
+  G.inv_gm1 = 1.0 / (g - 1.0);
+  return G;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t ctl, cell_off, dx, t, smax, tiles, snap, total;
+  long long max_tiles;
+  long long snap_doubles;
+};
+
+static bool problem_ok(const grprec_problem *p, long long *tc_out) {
+  if (!p) return false;
+  if (p->system != GRPREC_ADVECTION && p->system != GRPREC_EULER) return false;
+  if (p->order < 2 || p->order > 5) return false;
+  if (!(p->cfl > 0.0) || p->cfl > 1.0) return false;
+  if (p->bc != GRPREC_BC_PERIODIC && p->bc != GRPREC_BC_TRANSMISSIVE) return false;
+  if (p->n_segments < 1 || !p->seg_cells || !p->seg_length) return false;
+  if (p->bc == GRPREC_BC_PERIODIC && p->n_segments != 1) return false;
+  if (p->system == GRPREC_ADVECTION && !(p->lambda != 0.0 && std::isfinite(p->lambda))) return false;
+  if (p->system == GRPREC_EULER && !(p->gamma > 1.0)) return false;
+  long long tc = 0;
+  for (int s = 0; s < p->n_segments; ++s) {
+    if (p->seg_cells[s] < 2 || !(p->seg_length[s] > 0.0)) return false;
+    tc += p->seg_cells[s];
+  }
+  if (tc + p->n_segments > (long long)std::numeric_limits<int>::max() / 3) return false;
+  *tc_out = tc;
+  return true;
+}
+
+static Layout layout(const grprec_problem *p, long long tc) {
+  Layout L;
+  const long long S = p->n_segments;
+  const int nvar = p->system == GRPREC_EULER ? 3 : 1;
+  size_t o = 0;
+  L.ctl = o; o = align256(o + sizeof(Ctl));
+  L.cell_off = o; o = align256(o + sizeof(int) * (S + 1));
+  L.dx = o; o = align256(o + sizeof(double) * S);
+  L.t = o; o = align256(o + sizeof(double) * 3 * S);
+  L.smax = o; o = align256(o + sizeof(unsigned long long) * 3 * S);
+  L.max_tiles = (p->system == GRPREC_EULER) ? tc / 62 + S + 2 : 0;
+  L.tiles = o; o = align256(o + sizeof(int4) * L.max_tiles);
+  L.snap_doubles = (p->system == GRPREC_EULER && p->schedule == GRPREC_SCHED_AUTO)
+                       ? nvar * (2 * tc + S) + 6 * S
+                       : 0;
+  L.snap = o; o = align256(o + sizeof(double) * L.snap_doubles + (L.snap_doubles ? sizeof(Ctl) : 0));
+  L.total = o;
+  return L;
+}
+
+}  // namespace grp
+
+using namespace grp;
+
+struct grprec_handle {
+  grprec_problem p;
+  int nvar, M;
+  long long tc, ti;
+  int S;
+  std::vector<int> cell_off;
+  std::vector<double> dx;
+  double *q0, *q1, *v0, *v1;
+  char *work;
+  Layout L;
+  Ctl *ctl;
+  Seg seg;
+  int4 *tiles;
+  int ntiles;
+  int schedule, block, grid;
+  std::vector<int> dom_tile0;  // per-domain first tile (per-domain schedule)
+  hipStream_t stream, cap_stream;
+  int slot;
+  Gas gas;
+  StConst<1> C1;
+  StConst<2> C2;
+  StConst<3> C3;
+  Harvest hv;
+  Ctl *host_ctl;  // pinned read-back
+  double *host_buf;
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int n_cu;
+  double t_end_set;
+  const float *mlp;
+};
+
+static const int K_GRAPH = 30;  // steps per captured graph (a multiple of 3)
+
+static int hip_fail(hipError_t e) {
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "grprec: HIP error %s\n", hipGetErrorString(e));
+    return GRPREC_E_HIP;
+  }
+  return GRPREC_OK;
+}
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) return hip_fail(_e); \
+  } while (0)
+
+static int err_code(unsigned bits) {
+  if (bits & ERR_NONPHYS) return GRPREC_E_NONPHYSICAL;
+  if (bits & ERR_VACUUM) return GRPREC_E_VACUUM;
+  if (bits & ERR_NEWTON) return GRPREC_E_NEWTON;
+  if (bits & ERR_PICARD) return GRPREC_E_PREDICTOR;
+  return GRPREC_OK;
+}
+
+// ------------------------------------------------------------ tiles
+static std::vector<int4> build_tiles(grprec_handle *h, int schedule, int block) {
+  const int T = block - 2;
+  std::vector<int4> t;
+  const int S = h->S;
+  const std::vector<int> &off = h->cell_off;
+  auto seg_of = [&](int c) {
+    return int(std::upper_bound(off.begin(), off.end(), c) - off.begin()) - 1;
+  };
+  if (schedule == GRPREC_SCHED_FLAT_TILES) {
+    for (long long st = 0; st < h->tc; st += T) {
+      int cnt = (int)std::min<long long>(T, h->tc - st);
+      t.push_back(make_int4((int)st, cnt, seg_of((int)st), seg_of((int)(st + cnt - 1))));
+    }
+  } else if (schedule == GRPREC_SCHED_PACKED) {
+    int cur_start = -1, cur_cnt = 0, cur_s0 = 0;
+    auto flush = [&](int last_seg) {
+      if (cur_cnt > 0) t.push_back(make_int4(cur_start, cur_cnt, cur_s0, last_seg));
+      cur_cnt = 0;
+      cur_start = -1;
+    };
+    for (int s = 0; s < S; ++s) {
+      const int n = off[s + 1] - off[s];
+      if (n > T) {
+        flush(s - 1);
+        int pieces = (n + T - 1) / T;
+        int base = n / pieces, extra = n % pieces, st = off[s];
+        for (int k = 0; k < pieces; ++k) {
+          int cnt = base + (k < extra ? 1 : 0);
+          t.push_back(make_int4(st, cnt, s, s));
+          st += cnt;
+        }
+      } else {
+        if (cur_cnt + n > T) flush(s - 1);
+        if (cur_cnt == 0) {
+          cur_start = off[s];
+          cur_s0 = s;
+        }
+        cur_cnt += n;
+      }
+    }
+    flush(S - 1);
+  } else {  // segment tiles (also the per-domain schedule)
+    h->dom_tile0.assign(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+      h->dom_tile0[s] = (int)t.size();
+      for (int st = off[s]; st < off[s + 1]; st += T) {
+        int cnt = std::min(T, off[s + 1] - st);
+        t.push_back(make_int4(st, cnt, s, s));
+      }
+    }
+    h->dom_tile0[S] = (int)t.size();
+  }
+  return t;
+}
+
+static int euler_occ(int M, int block, int *occ) {
+  hipError_t e;
+  switch (M) {
+    case 1: e = euler_occupancy<1>(block, occ); break;
+    case 2: e = euler_occupancy<2>(block, occ); break;
+    default: e = euler_occupancy<3>(block, occ); break;
+  }
+  return hip_fail(e);
+}
+
+static int apply_schedule(grprec_handle *h, int schedule, int block) {
+  std::vector<int4> t = build_tiles(h, schedule, block);
+  if ((long long)t.size() > h->L.max_tiles) return GRPREC_E_INVALID;
+  HIPCHK(hipMemcpyAsync(h->tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->ntiles = (int)t.size();
+  h->schedule = schedule;
+  h->block = block;
+  int occ = 1;
+  int rc = euler_occ(h->M, block, &occ);
+  if (rc) return rc;
+  if (occ < 1) occ = 1;
+  long long g = (long long)occ * h->n_cu;
+  h->grid = (int)std::max<long long>(1, std::min<long long>(g, h->ntiles));
+  if (h->graph_ok) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph_ok = false;
+  }
+  return GRPREC_OK;
+}
+
+// ------------------------------------------------------------ launches
+template <int M>
+static EulerArgs<M> euler_args(const grprec_handle *h, int slot, const StConst<M> &C) {
+  EulerArgs<M> a;
+  a.q0 = h->q0; a.q1 = h->q1; a.v0 = h->v0; a.v1 = h->v1;
+  a.tc = (int)h->tc; a.ti = (int)h->ti;
+  a.tiles = h->tiles; a.ntiles = h->ntiles;
+  a.seg = h->seg;
+  a.ctl = h->ctl;
+  a.slot = slot;
+  a.periodic = h->p.bc == GRPREC_BC_PERIODIC;
+  a.cfl = h->p.cfl;
+  a.gas = h->gas;
+  a.max_newton = h->p.max_newton;
+  a.newton_tol = h->p.newton_tol;
+  a.max_picard = h->p.max_picard;
+  a.picard_tol = h->p.picard_tol;
+  a.guess = h->p.guess;
+  a.warm = h->p.warm_start;
+  a.gate = h->p.mlp_gate;
+  a.mlp = h->mlp;
+  a.hv = h->hv;
+  a.C = C;
+  return a;
+}
+
+template <int M>
+static AdvArgs<M> adv_args(const grprec_handle *h, int slot) {
+  AdvArgs<M> a;
+  a.q0 = h->q0; a.q1 = h->q1; a.v0 = h->v0; a.v1 = h->v1;
+  a.n = (int)h->tc;
+  a.seg = h->seg;
+  a.ctl = h->ctl;
+  a.slot = slot;
+  a.periodic = h->p.bc == GRPREC_BC_PERIODIC;
+  a.cfl = h->p.cfl;
+  a.lambda = h->p.lambda;
+  return a;
+}
+
+template <int M>
+static hipError_t launch_per_domain(grprec_handle *h, int slot, const StConst<M> &C, hipStream_t st) {
+  EulerArgs<M> a = euler_args<M>(h, slot, C);
+  for (int s = 0; s < h->S; ++s) {
+    const int t0 = h->dom_tile0[s], nt = h->dom_tile0[s + 1] - t0;
+    a.tiles = h->tiles + t0;
+    a.ntiles = nt;
+    hipError_t e = launch_euler<M>(a, h->block, nt, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t launch_step(grprec_handle *h, int slot, hipStream_t st) {
+  if (h->p.system == GRPREC_EULER && h->schedule == GRPREC_SCHED_PER_DOMAIN) {
+    switch (h->M) {
+      case 1: return launch_per_domain<1>(h, slot, h->C1, st);
+      case 2: return launch_per_domain<2>(h, slot, h->C2, st);
+      default: return launch_per_domain<3>(h, slot, h->C3, st);
+    }
+  }
+  if (h->p.system == GRPREC_EULER) {
+    switch (h->M) {
+      case 1: return launch_euler<1>(euler_args<1>(h, slot, h->C1), h->block, h->grid, st);
+      case 2: return launch_euler<2>(euler_args<2>(h, slot, h->C2), h->block, h->grid, st);
+      default: return launch_euler<3>(euler_args<3>(h, slot, h->C3), h->block, h->grid, st);
+    }
+  }
+  long long g = (h->tc + 255) / 256;
+  int grid = (int)std::max<long long>(1, std::min<long long>(g, 1 << 20));
+  switch (h->M) {
+    case 1: return launch_adv<1>(adv_args<1>(h, slot), grid, st);
+    case 2: return launch_adv<2>(adv_args<2>(h, slot), grid, st);
+    case 3: return launch_adv<3>(adv_args<3>(h, slot), grid, st);
+    default: return launch_adv<4>(adv_args<4>(h, slot), grid, st);
+  }
+}
+
+static int eager_step(grprec_handle *h) {
+  HIPCHK(launch_step(h, h->slot, h->stream));
+  h->slot = (h->slot + 1) % 3;
+  return GRPREC_OK;
+}
+
+static int ensure_graph(grprec_handle *h) {
+  if (h->graph_ok) return GRPREC_OK;
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < K_GRAPH; ++k) {
+    hipError_t e = launch_step(h, k % 3, h->cap_stream);
+    if (e != hipSuccess) {
+      (void)hipStreamEndCapture(h->cap_stream, &g);
+      return hip_fail(e);
+    }
+  }
+  HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  h->graph_ok = true;
+  return GRPREC_OK;
+}
+
+static int issue_steps(grprec_handle *h, long long k) {
+  if (h->schedule == GRPREC_SCHED_PER_DOMAIN) {  // plain form: no graphs
+    for (; k > 0; --k) {
+      int rc = eager_step(h);
+      if (rc) return rc;
+    }
+    return GRPREC_OK;
+  }
+  while (k > 0 && h->slot != 0) {
+    int rc = eager_step(h);
+    if (rc) return rc;
+    --k;
+  }
+  if (k >= K_GRAPH) {
+    int rc = ensure_graph(h);
+    if (rc) return rc;
+    while (k >= K_GRAPH) {
+      HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      k -= K_GRAPH;
+    }
+  }
+  while (k > 0) {
+    int rc = eager_step(h);
+    if (rc) return rc;
+    --k;
+  }
+  return GRPREC_OK;
+}
+
+static int read_ctl(grprec_handle *h) {
+  HIPCHK(hipMemcpyAsync(h->host_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return GRPREC_OK;
+}
+
+static int prologue(grprec_handle *h, double t_end) {
+  HIPCHK(launch_run_prologue(h->ctl, h->seg, h->slot, t_end, h->stream));
+  h->t_end_set = t_end;
+  return GRPREC_OK;
+}
+
+// ------------------------------------------------------------ C ABI
+extern "C" {
+
+size_t grprec_workspace_bytes(const grprec_problem *p) {
+  long long tc;
+  if (!problem_ok(p, &tc)) return 0;
+  return layout(p, tc).total;
+}
+
+const char *grprec_error_string(int code) {
+  switch (code) {
+    case GRPREC_OK: return "ok";
+    case GRPREC_E_INVALID: return "invalid argument";
+    case GRPREC_E_UNSUPPORTED: return "unsupported configuration";
+    case GRPREC_E_HIP: return "HIP runtime error";
+    case GRPREC_E_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+    case GRPREC_E_VACUUM: return "Riemann data generate vacuum";
+    case GRPREC_E_NEWTON: return "star-pressure Newton iteration did not converge";
+    case GRPREC_E_PREDICTOR: return "space-time predictor did not converge";
+    default: return "unknown error";
+  }
+}
+
+void grprec_destroy(grprec_handle *h) {
+  if (!h) return;
+  if (h->graph_ok) (void)hipGraphExecDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+  if (h->host_buf) (void)hipHostFree(h->host_buf);
+  delete h;
+}
+
+int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buffers *b,
+                void *hip_stream) {
+  if (!out) return GRPREC_E_INVALID;
+  *out = nullptr;
+  long long tc;
+  if (!problem_ok(pin, &tc) || !b) return GRPREC_E_INVALID;
+  if (!b->q0 || !b->q1 || !b->v0 || !b->v1 || !b->work) return GRPREC_E_INVALID;
+  grprec_problem p = *pin;
+  if (p.system == GRPREC_EULER && p.order > 4) return GRPREC_E_UNSUPPORTED;
+  if (p.system == GRPREC_ADVECTION && p.n_segments != 1) return GRPREC_E_UNSUPPORTED;
+  if (p.max_newton <= 0) p.max_newton = 50;
+  if (!(p.newton_tol > 0.0)) p.newton_tol = 1e-12;
+  if (p.max_picard <= 0) p.max_picard = 64;
+  if (!(p.picard_tol > 0.0)) p.picard_tol = 1e-13;
+  if (p.mlp_gate == 0.0) p.mlp_gate = 0.1;
+  if (p.guess == GRPREC_GUESS_MLP && !p.mlp_params) return GRPREC_E_INVALID;
+  if (p.block != 0 && p.block != 64 && p.block != 128 && p.block != 256) return GRPREC_E_INVALID;
+  if (p.schedule < GRPREC_SCHED_AUTO || p.schedule > GRPREC_SCHED_PER_DOMAIN) return GRPREC_E_INVALID;
+  Layout L = layout(&p, tc);
+  if (b->work_bytes < L.total) return GRPREC_E_INVALID;
+
+  grprec_handle *h = new grprec_handle();
+  h->p = p;
+  h->p.seg_cells = nullptr;  // host arrays are not kept
+  h->p.seg_length = nullptr;
+  h->nvar = p.system == GRPREC_EULER ? 3 : 1;
+  h->M = p.order - 1;
+  h->S = p.n_segments;
+  h->tc = tc;
+  h->ti = tc + p.n_segments;
+  h->q0 = b->q0; h->q1 = b->q1; h->v0 = b->v0; h->v1 = b->v1;
+  h->work = (char *)b->work;
+  h->L = L;
+  h->stream = (hipStream_t)hip_stream;
+  h->mlp = p.mlp_params;
+  h->gas = make_gas(p.system == GRPREC_EULER ? p.gamma : 1.4);
+  h->hv.ring = nullptr;
+  h->hv.cap = 0;
+  h->hv.count = nullptr;
+  h->ctl = (Ctl *)(h->work + L.ctl);
+  h->seg.cell_off = (const int *)(h->work + L.cell_off);
+  h->seg.dx = (const double *)(h->work + L.dx);
+  h->seg.t = (double *)(h->work + L.t);
+  h->seg.smax = (unsigned long long *)(h->work + L.smax);
+  h->seg.S = h->S;
+  h->tiles = (int4 *)(h->work + L.tiles);
+  int rc = GRPREC_OK;
+  auto fail = [&](int code) {
+    grprec_destroy(h);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(GRPREC_E_HIP);
+  if (hipHostMalloc((void **)&h->host_ctl, sizeof(Ctl)) != hipSuccess) return fail(GRPREC_E_HIP);
+  if (hipHostMalloc((void **)&h->host_buf, sizeof(double) * (3 * (size_t)h->S + 16)) != hipSuccess)
+    return fail(GRPREC_E_HIP);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(GRPREC_E_HIP);
+
+  if (h->M == 1) st_constants<1>(h->C1);
+  if (h->M == 2) st_constants<2>(h->C2);
+  if (h->M == 3) st_constants<3>(h->C3);
+
+  h->cell_off.resize(h->S + 1);
+  h->dx.resize(h->S);
+  h->cell_off[0] = 0;
+  for (int s = 0; s < h->S; ++s) {
+    h->cell_off[s + 1] = h->cell_off[s] + (int)pin->seg_cells[s];
+    h->dx[s] = pin->seg_length[s] / (double)pin->seg_cells[s];
+  }
+  if (hipMemcpyAsync((void *)h->seg.cell_off, h->cell_off.data(), sizeof(int) * (h->S + 1),
+                     hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return fail(GRPREC_E_HIP);
+  if (hipMemcpyAsync((void *)h->seg.dx, h->dx.data(), sizeof(double) * h->S, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess)
+    return fail(GRPREC_E_HIP);
+  const double smax_const = p.system == GRPREC_ADVECTION ? std::fabs(p.lambda) : 0.0;
+  if (launch_reset_ctl(h->ctl, h->seg, 0.0, 0, 0, smax_const, h->stream) != hipSuccess) return fail(GRPREC_E_HIP);
+  hipError_t e;
+  if (p.system == GRPREC_EULER) {
+    e = launch_init_interfaces_euler(h->v0, h->v1, (int)h->ti, h->gas, p.max_newton, p.newton_tol, h->ctl,
+                                     h->stream);
+    if (e == hipSuccess) e = launch_domain_smax(h->q0, (int)h->tc, h->seg, 0, h->gas, h->ctl, h->stream);
+  } else {
+    e = launch_init_interfaces_adv(h->v0, h->v1, (int)h->ti, p.lambda, h->stream);
+  }
+  if (e != hipSuccess) return fail(hip_fail(e));
+  h->slot = 0;
+  h->t_end_set = -1.0;
+  if (p.system == GRPREC_EULER) {
+    int sched = p.schedule == GRPREC_SCHED_AUTO ? GRPREC_SCHED_PACKED : p.schedule;
+    int blk = p.block ? p.block : 256;
+    if (h->S == 1 && p.schedule == GRPREC_SCHED_AUTO) sched = GRPREC_SCHED_SEGMENT_TILES;
+    rc = apply_schedule(h, sched, blk);
+    if (rc) return fail(rc);
+  }
+  rc = read_ctl(h);
+  if (rc) return fail(rc);
+  rc = err_code(h->host_ctl->err);
+  if (rc) return fail(rc);
+  if (p.system == GRPREC_EULER && p.schedule == GRPREC_SCHED_AUTO && h->tc >= 4096) {
+    int n;
+    double ms[9];
+    rc = grprec_autotune(h, 3, ms, 9, &n);
+    if (rc) return fail(rc);
+  }
+  *out = h;
+  return GRPREC_OK;
+}
+
+int grprec_step(grprec_handle *h, double t_stop, double *dt_out) {
+  if (!h) return GRPREC_E_INVALID;
+  double t0 = 0.0;
+  if (dt_out) {
+    HIPCHK(hipMemcpyAsync(h->host_buf, h->seg.t + h->slot * h->S, sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    t0 = h->host_buf[0];
+  }
+  int rc = prologue(h, t_stop);
+  if (rc) return rc;
+  rc = eager_step(h);
+  if (rc) return rc;
+  if (dt_out) {
+    HIPCHK(hipMemcpyAsync(h->host_buf, h->seg.t + h->slot * h->S, sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    rc = read_ctl(h);
+    if (rc) return rc;
+    *dt_out = h->host_buf[0] - t0;
+    return err_code(h->host_ctl->err);
+  }
+  return GRPREC_OK;
+}
+
+int grprec_run(grprec_handle *h, double t_end, int64_t max_steps, int64_t *steps_out, double *t_out) {
+  if (!h || max_steps < 0) return GRPREC_E_INVALID;
+  int rc = prologue(h, t_end);
+  if (rc) return rc;
+  rc = read_ctl(h);
+  if (rc) return rc;
+  const long long steps0 = h->host_ctl->steps[h->slot];
+  long long issued = 0;
+  while (true) {
+    const Ctl &c = *h->host_ctl;
+    rc = err_code(c.err);
+    if (rc) break;
+    if (c.active[h->slot] == 0 || issued >= max_steps) break;
+    long long chunk = max_steps - issued;
+    if (h->S == 1) {
+      // estimate of the steps left from the current dt; never more than 4 graphs ahead
+      HIPCHK(hipMemcpyAsync(h->host_buf, h->seg.t + h->slot * h->S, sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+      HIPCHK(hipMemcpyAsync(h->host_buf + 1, h->seg.smax + h->slot * h->S, sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      double t = h->host_buf[0], S;
+      std::memcpy(&S, h->host_buf + 1, sizeof(double));
+      double dt = h->p.cfl * h->dx[0] / S;
+      double est = std::ceil((t_end - t) / dt * 1.0000001) + 1;
+      if (std::isfinite(est) && est >= 1) chunk = std::min<long long>(chunk, (long long)est);
+    }
+    chunk = std::min<long long>(chunk, 4LL * 1024 * K_GRAPH);
+    rc = issue_steps(h, chunk);
+    if (rc) return rc;
+    issued += chunk;
+    rc = read_ctl(h);
+    if (rc) return rc;
+  }
+  if (steps_out) *steps_out = h->host_ctl->steps[h->slot] - steps0;
+  if (t_out) {
+    HIPCHK(hipMemcpyAsync(h->host_buf, h->seg.t + h->slot * h->S, sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *t_out = h->host_buf[0];
+  }
+  return rc;
+}
+
+int grprec_state(grprec_handle *h, int *current, double *t_min, double *t_max, int64_t *steps) {
+  if (!h) return GRPREC_E_INVALID;
+  std::vector<double> t(h->S);
+  HIPCHK(hipMemcpyAsync(t.data(), h->seg.t + h->slot * h->S, sizeof(double) * h->S, hipMemcpyDeviceToHost,
+                        h->stream));
+  int rc = read_ctl(h);
+  if (rc) return rc;
+  if (current) *current = h->host_ctl->cur[h->slot];
+  if (steps) *steps = h->host_ctl->steps[h->slot];
+  if (t_min) *t_min = *std::min_element(t.begin(), t.end());
+  if (t_max) *t_max = *std::max_element(t.begin(), t.end());
+  return err_code(h->host_ctl->err);
+}
+
+int grprec_segment_times(grprec_handle *h, double *t_host) {
+  if (!h || !t_host) return GRPREC_E_INVALID;
+  HIPCHK(hipMemcpyAsync(t_host, h->seg.t + h->slot * h->S, sizeof(double) * h->S, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return GRPREC_OK;
+}
+
+int grprec_set_state(grprec_handle *h, int current, double t, int64_t steps) {
+  if (!h || (current != 0 && current != 1)) return GRPREC_E_INVALID;
+  const double smax_const = h->p.system == GRPREC_ADVECTION ? std::fabs(h->p.lambda) : 0.0;
+  HIPCHK(launch_reset_ctl(h->ctl, h->seg, t, steps, current, smax_const, h->stream));
+  if (h->p.system == GRPREC_EULER)
+    HIPCHK(launch_domain_smax(current ? h->q1 : h->q0, (int)h->tc, h->seg, 0, h->gas, h->ctl, h->stream));
+  h->slot = 0;
+  int rc = read_ctl(h);
+  if (rc) return rc;
+  return err_code(h->host_ctl->err);
+}
+
+int grprec_get_schedule(grprec_handle *h, int *schedule, int *block) {
+  if (!h) return GRPREC_E_INVALID;
+  if (schedule) *schedule = h->schedule;
+  if (block) *block = h->block;
+  return GRPREC_OK;
+}
+
+int grprec_set_schedule(grprec_handle *h, int schedule, int block) {
+  if (!h || h->p.system != GRPREC_EULER) return GRPREC_E_INVALID;
+  if (schedule < GRPREC_SCHED_SEGMENT_TILES || schedule > GRPREC_SCHED_PER_DOMAIN) return GRPREC_E_INVALID;
+  if (block != 64 && block != 128 && block != 256) return GRPREC_E_INVALID;
+  return apply_schedule(h, schedule, block);
+}
+
+int grprec_autotune(grprec_handle *h, int steps, double *ms_out, int n_max, int *n_out) {
+  if (!h || h->p.system != GRPREC_EULER || steps < 1) return GRPREC_E_INVALID;
+  if (h->L.snap_doubles == 0) return GRPREC_E_INVALID;  // workspace has no snapshot area
+  // snapshot: current q and v, domain times and S_max of the slot, control block
+  int rc = read_ctl(h);
+  if (rc) return rc;
+  const int cur = h->host_ctl->cur[h->slot];
+  double *snap = (double *)(h->work + h->L.snap);
+  const size_t nq = (size_t)h->nvar * h->tc, nv = (size_t)h->nvar * h->ti;
+  double *sq = snap, *sv = snap + nq, *sseg = sv + nv;
+  Ctl *sctl = (Ctl *)(snap + h->L.snap_doubles);
+  double *qc = cur ? h->q1 : h->q0, *vc = cur ? h->v1 : h->v0;
+  HIPCHK(hipMemcpyAsync(sq, qc, sizeof(double) * nq, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(sv, vc, sizeof(double) * nv, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(sseg, h->seg.t, sizeof(double) * 3 * h->S, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(sseg + 3 * h->S, h->seg.smax, sizeof(double) * 3 * h->S, hipMemcpyDeviceToDevice,
+                        h->stream));
+  HIPCHK(hipMemcpyAsync(sctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, h->stream));
+  const int slot0 = h->slot;
+  const double tend0 = h->t_end_set;
+  auto restore = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(qc, sq, sizeof(double) * nq, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(vc, sv, sizeof(double) * nv, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->seg.t, sseg, sizeof(double) * 3 * h->S, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->seg.smax, sseg + 3 * h->S, sizeof(double) * 3 * h->S, hipMemcpyDeviceToDevice,
+                          h->stream));
+    HIPCHK(hipMemcpyAsync(h->ctl, sctl, sizeof(Ctl), hipMemcpyDeviceToDevice, h->stream));
+    h->slot = slot0;
+    h->t_end_set = tend0;
+    return GRPREC_OK;
+  };
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int scheds[3] = {GRPREC_SCHED_SEGMENT_TILES, GRPREC_SCHED_FLAT_TILES, GRPREC_SCHED_PACKED};
+  const int blocks[3] = {64, 128, 256};
+  int nres = 0, best_s = h->schedule, best_b = h->block;
+  double best_ms = 1e300;
+  unsigned long long ref_hash[2] = {0, 0};
+  bool have_ref = false;
+  for (int si = 0; si < 3 && rc == GRPREC_OK; ++si) {
+    for (int bi = 0; bi < 3 && rc == GRPREC_OK; ++bi) {
+      if (h->S == 1 && scheds[si] != GRPREC_SCHED_SEGMENT_TILES) continue;
+      rc = apply_schedule(h, scheds[si], blocks[bi]);
+      if (rc) break;
+      rc = restore();
+      if (rc) break;
+      rc = prologue(h, std::numeric_limits<double>::infinity());
+      if (rc) break;
+      rc = eager_step(h);  // warm-up (also first touch of code)
+      if (rc) break;
+      rc = restore();
+      if (rc) break;
+      rc = prologue(h, std::numeric_limits<double>::infinity());
+      if (rc) break;
+      HIPCHK(hipEventRecord(e0, h->stream));
+      for (int k = 0; k < steps && rc == GRPREC_OK; ++k) rc = eager_step(h);
+      HIPCHK(hipEventRecord(e1, h->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      // digest of the resulting state
+      rc = read_ctl(h);
+      if (rc) break;
+      const int c2 = h->host_ctl->cur[h->slot];
+      HIPCHK(hipMemsetAsync(&h->ctl->hash[0], 0, 2 * sizeof(unsigned long long), h->stream));
+      HIPCHK(launch_digest(c2 ? h->q1 : h->q0, (long long)nq, h->ctl, h->stream));
+      HIPCHK(launch_digest(c2 ? h->v1 : h->v0, (long long)nv, h->ctl, h->stream));
+      rc = read_ctl(h);
+      if (rc) break;
+      bool same = true;
+      if (!have_ref) {
+        ref_hash[0] = h->host_ctl->hash[0];
+        ref_hash[1] = h->host_ctl->hash[1];
+        have_ref = true;
+      } else {
+        same = ref_hash[0] == h->host_ctl->hash[0] && ref_hash[1] == h->host_ctl->hash[1];
+      }
+      const double per = ms / steps;
+      if (ms_out && nres < n_max) ms_out[nres] = same ? per : -per;
+      ++nres;
+      if (same && per < best_ms) {
+        best_ms = per;
+        best_s = scheds[si];
+        best_b = blocks[bi];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc2 = restore();
+  if (rc == GRPREC_OK) rc = rc2;
+  if (rc == GRPREC_OK) rc = apply_schedule(h, best_s, best_b);
+  if (n_out) *n_out = nres;
+  return rc;
+}
+
+int grprec_enable_stats(grprec_handle *h, int on) {
+  if (!h) return GRPREC_E_INVALID;
+  unsigned v = on ? 1u : 0u;
+  HIPCHK(hipMemcpyAsync(&h->ctl->stats_on, &v, sizeof(unsigned), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return GRPREC_OK;
+}
+
+int grprec_get_stats(grprec_handle *h, grprec_stats *out) {
+  if (!h || !out) return GRPREC_E_INVALID;
+  int rc = read_ctl(h);
+  if (rc) return rc;
+  out->rs_calls = h->host_ctl->stat[0];
+  out->newton_iters = h->host_ctl->stat[1];
+  out->picard_sweeps = h->host_ctl->stat[2];
+  out->cells_predicted = h->host_ctl->stat[3];
+  out->mlp_guesses = h->host_ctl->stat[4];
+  return GRPREC_OK;
+}
+
+int grprec_harvest(grprec_handle *h, double *ring, int64_t cap, int64_t *count_dev) {
+  if (!h || h->p.system != GRPREC_EULER) return GRPREC_E_INVALID;
+  if (ring && (!count_dev || cap < 1)) return GRPREC_E_INVALID;
+  h->hv.ring = ring;
+  h->hv.cap = ring ? cap : 0;
+  h->hv.count = ring ? (unsigned long long *)count_dev : nullptr;
+  if (h->graph_ok) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph_ok = false;
+  }
+  return GRPREC_OK;
+}
+
+}  // extern "C"

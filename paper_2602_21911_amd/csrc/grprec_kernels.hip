@@ -1,0 +1,784 @@
+// grprec_kernels.hip -- gfx950 kernels of the GRPrec finite-volume step.
+//
+// One launch advances every domain by one step:
+//   dt from S_max (eq. dt-FV) -> GRPrec reconstruction (Sec. 3.1) -> DET
+//   space-time predictor -> Riemann problems at the Gauss-Legendre times of the
+//   flux integral (eq. numfluxes) and at tau = dt (next step's interface data)
+//   -> conservative update (eq. eq_finite_volume) -> S_max of the new state.
+// FP64 throughout; no matrix cores: the work is a per-cell stencil, not a
+// dense contraction.
+#include <hip/hip_runtime.h>
+
+#include "grprec_device.h"
+#include "grprec_internal.h"
+
+namespace grp {
+
+// Per-domain step size from the slot's time and S_max: dt = cfl dx / S,
+// clipped so that the domain lands exactly on t_end; dt = 0 for finished
+// domains.
+__device__ __forceinline__ void domain_dt(double cfl, double dx, double S, double t, double t_end,
+                                          double &dt, double &t_new, bool &done) {
+  done = !(t < t_end);
+  if (done) {
+    dt = 0.0;
+    t_new = t;
+    return;
+  }
+  double d = cfl * dx / S;
+  if (d >= t_end - t) {
+    dt = t_end - t;
+    t_new = t_end;
+  } else {
+    dt = d;
+    t_new = t + d;
+  }
+}
+
+// Step launched when no domain is active: carry the slot forward unchanged.
+__device__ void carry_slot(const Seg &seg, Ctl *ctl, int slot) {
+  const int s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) {
+    ctl->cur[s1] = ctl->cur[slot];
+    ctl->steps[s1] = ctl->steps[slot];
+    ctl->active[s2] = 0;
+  }
+  for (int s = gid; s < seg.S; s += gridDim.x * blockDim.x) {
+    seg.t[s1 * seg.S + s] = seg.t[slot * seg.S + s];
+    seg.smax[s1 * seg.S + s] = seg.smax[slot * seg.S + s];
+    seg.smax[s2 * seg.S + s] = 0ull;
+  }
+}
+
+__device__ __forceinline__ int find_domain(const int *cell_off, int c, int lo, int hi) {
+  // largest s in [lo, hi] with cell_off[s] <= c
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cell_off[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ============================================================ Euler step
+template <int M, int B>
+__global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
+  constexpr int N = M + 1;   // nodes per direction
+  constexpr int NT = M + 2;  // trace times: N Gauss-Legendre times and tau = 1
+  __shared__ double sTL[3 * NT][B];
+  __shared__ double sTR[3 * NT][B];
+  __shared__ double sF[3][B];
+  __shared__ double sV[3][B];
+
+  Ctl *ctl = a.ctl;
+  const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
+  if (ctl->active[slot] == 0) {
+    carry_slot(a.seg, ctl, slot);
+    return;
+  }
+  const int cur = ctl->cur[slot];
+  const double *__restrict__ qin = cur ? a.q1 : a.q0;
+  double *__restrict__ qout = cur ? a.q0 : a.q1;
+  const double *__restrict__ vin = cur ? a.v1 : a.v0;
+  double *__restrict__ vout = cur ? a.v0 : a.v1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->cur[s1] = 1 - cur;
+    ctl->steps[s1] = ctl->steps[slot] + 1;
+    ctl->active[s2] = 0;
+  }
+  const double t_end = ctl->t_end;
+  const bool stats = ctl->stats_on != 0;
+  const Gas &G = a.gas;
+  const int e = threadIdx.x;
+  const int tc = a.tc, ti = a.ti;
+  unsigned err = 0;
+  unsigned long long st_rs = 0, st_newton = 0, st_sweeps = 0, st_cells = 0, st_mlp = 0;
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int4 td = a.tiles[tile];
+    const int start = td.x, count = td.y;
+    // ---- which cell this slot holds
+    bool valid = false, useful = false;
+    int c = 0, s = td.z;
+    if (e >= 1 && e <= count) {
+      c = start + e - 1;
+      s = (td.z == td.w) ? td.z : find_domain(a.seg.cell_off, c, td.z, td.w);
+      valid = useful = true;
+    } else if (e == 0) {
+      s = td.z;
+      const int off = a.seg.cell_off[s], end = a.seg.cell_off[s + 1];
+      if (start > off) { c = start - 1; valid = true; }
+      else if (a.periodic) { c = end - 1; valid = true; }
+    } else if (e == count + 1) {
+      s = td.w;
+      const int off = a.seg.cell_off[s], end = a.seg.cell_off[s + 1];
+      const int last = start + count - 1;
+      if (last + 1 < end) { c = last + 1; valid = true; }
+      else if (a.periodic) { c = off; valid = true; }
+    }
+    int off = 0, n = 1, i = 0, io = 0;
+    double dx = 1.0, dt = 0.0, t_new = 0.0, nu = 0.0, t = 0.0;
+    bool done = true;
+    if (valid) {
+      off = a.seg.cell_off[s];
+      n = a.seg.cell_off[s + 1] - off;
+      i = c - off;
+      io = off + s;
+      dx = a.seg.dx[s];
+      t = a.seg.t[slot * a.seg.S + s];
+      const double S = bitsd(a.seg.smax[slot * a.seg.S + s]);
+      domain_dt(a.cfl, dx, S, t, t_end, dt, t_new, done);
+      nu = dt / dx;
+    }
+    const bool work = valid && !done;
+
+    // ---- load, reconstruct, predict
+    double q0[3];
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) q0[v] = qin[v * tc + c];
+    }
+    if (work) {
+      int im = i - 1, ip = i + 1;
+      if (a.periodic) {
+        if (im < 0) im += n;
+        if (ip >= n) ip -= n;
+      } else {
+        if (im < 0) im = 0;
+        if (ip >= n) ip = n - 1;
+      }
+      double w[3][N];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const double qc = q0[v];
+        const double vl = vin[v * ti + io + i], vr = vin[v * ti + io + i + 1];
+        const double DI = vr - vl, SI = vl + vr - 2.0 * qc;
+        double a1, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+        if (M == 1) {
+          a1 = DI;
+        } else if (M == 2) {
+          a1 = DI;
+          a2 = 3.0 * SI;
+        } else {
+          const double qm = qin[v * tc + off + im], qp = qin[v * tc + off + ip];
+          const double DC = qp - qm, SC = qp + qm - 2.0 * qc;
+          a1 = 1.25 * DI - 0.125 * DC;
+          a3 = 0.5 * DC - DI;
+          if (M == 3) {
+            a2 = (3.0 * SI + 18.0 * SC) * (1.0 / 37.0);
+          } else {
+            a2 = 3.75 * SI - 0.125 * SC;
+            a4 = (5.0 / 12.0) * SC - 2.5 * SI;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+          w[v][k] = qc + a1 * a.C.phi[k][0] + a2 * a.C.phi[k][1] + a3 * a.C.phi[k][2] +
+                    a4 * a.C.phi[k][3];
+      }
+      // Picard iteration of the space-time Galerkin equations
+      double qh[3][N][N];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+#pragma unroll
+          for (int y = 0; y < N; ++y) qh[v][x][y] = w[v][x];
+      bool conv = false;
+      int it = 1;
+      for (; it <= a.max_picard; ++it) {
+        double F[3][N][N];
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+#pragma unroll
+          for (int y = 0; y < N; ++y)
+            euler_flux(G, qh[0][x][y], qh[1][x][y], qh[2][x][y], F[0][x][y], F[1][x][y], F[2][x][y]);
+        double diff = 0.0, nrm = 0.0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            double Gd[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              double acc = 0.0;
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc += a.C.D[x][k] * F[v][k][l];
+              Gd[l] = acc;
+            }
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+              double acc = 0.0;
+#pragma unroll
+              for (int l = 0; l < N; ++l) acc += a.C.KW[b][l] * Gd[l];
+              const double nv = w[v][x] - nu * acc;
+              diff = nanmax(diff, fabs(nv - qh[v][x][b]));
+              nrm = fmax(nrm, fabs(nv));
+              qh[v][x][b] = nv;
+            }
+          }
+        }
+        if (diff != diff) break;
+        if (diff <= a.picard_tol * (1.0 + nrm)) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv) err |= ERR_PICARD;
+      st_sweeps += conv ? it : a.max_picard;
+      st_cells += 1;
+      // traces at xi = 0 and xi = 1, times g_b and 1, staged in LDS
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double l1sum = 0.0, r1sum = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          double l = 0.0, r = 0.0;
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            l += a.C.l0[x] * qh[v][x][b];
+            r += a.C.l1[x] * qh[v][x][b];
+          }
+          sTL[v * NT + b][e] = l;
+          sTR[v * NT + b][e] = r;
+        }
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          double at1 = 0.0;
+#pragma unroll
+          for (int b = 0; b < N; ++b) at1 += a.C.l1[b] * qh[v][x][b];
+          l1sum += a.C.l0[x] * at1;
+          r1sum += a.C.l1[x] * at1;
+        }
+        sTL[v * NT + N][e] = l1sum;
+        sTR[v * NT + N][e] = r1sum;
+      }
+    }
+    __syncthreads();
+
+    // ---- interface x_{i+1/2}: Riemann problems at the trace times.  At a
+    // transmissive end the outside data are a ghost cell holding the end
+    // cell's average, constant in space and time.
+    double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
+    if (work && (useful || e == 0)) {
+      const bool boundary = (!a.periodic) && (i == n - 1);
+      double pw = 0.0;
+#pragma unroll 1
+      for (int b = 0; b < NT; ++b) {
+        double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
+        double f[3], qs[3];
+        {
+          double QR[3];
+          if (boundary) {
+            QR[0] = q0[0]; QR[1] = q0[1]; QR[2] = q0[2];
+          } else {
+            QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+          }
+          RSOut o;
+          err |= interact(G, QL, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp,
+                          a.max_newton, a.newton_tol, o);
+          pw = o.pstar;
+          st_rs += 1;
+          st_newton += o.iters;
+          st_mlp += o.mlp ? 1 : 0;
+          if (b == 0 && a.hv.ring != nullptr && useful) {
+            unsigned long long k = atomicAdd(a.hv.count, 1ull);
+            if ((long long)k < a.hv.cap) {
+              Prim L, R;
+              to_prim(G, QL[0], QL[1], QL[2], L);
+              to_prim(G, QR[0], QR[1], QR[2], R);
+              double *dst = a.hv.ring + 7 * k;
+              dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
+              dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
+              dst[6] = o.pstar;
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 3; ++v) { f[v] = o.F[v]; qs[v] = o.Q[v]; }
+        }
+        if (b < N) {
+          const double wb = a.C.w[b];
+#pragma unroll
+          for (int v = 0; v < 3; ++v) FR[v] += wb * f[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) VR[v] = qs[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        sF[v][e] = FR[v];
+        sV[v][e] = VR[v];
+      }
+    }
+    // left end of a transmissive domain: ghost average against the left trace
+    double FL[3] = {0.0, 0.0, 0.0}, VL[3] = {0.0, 0.0, 0.0};
+    if (work && useful && i == 0 && !a.periodic) {
+      double pw = 0.0;
+#pragma unroll 1
+      for (int b = 0; b < NT; ++b) {
+        double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
+        RSOut o;
+        err |= interact(G, q0, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp, a.max_newton,
+                        a.newton_tol, o);
+        pw = o.pstar;
+        st_rs += 1;
+        st_newton += o.iters;
+        st_mlp += o.mlp ? 1 : 0;
+        if (b < N) {
+          const double wb = a.C.w[b];
+#pragma unroll
+          for (int v = 0; v < 3; ++v) FL[v] += wb * o.F[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) VL[v] = o.Q[v];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- conservative update and S_max of the new state
+    double smax_i = 0.0;
+    int seg_tag = -1;
+    if (useful) {
+      double qn[3];
+      if (work) {
+        if (i > 0 || a.periodic) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            FL[v] = sF[v][e - 1];
+            VL[v] = sV[v][e - 1];
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) qn[v] = q0[v] - nu * (FR[v] - FL[v]);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) vout[v * ti + io + i + 1] = VR[v];
+        if (i == 0) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) vout[v * ti + io] = VL[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          qn[v] = q0[v];
+          vout[v * ti + io + i + 1] = vin[v * ti + io + i + 1];
+          if (i == 0) vout[v * ti + io] = vin[v * ti + io];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 3; ++v) qout[v * tc + c] = qn[v];
+      Prim W;
+      if (!to_prim(G, qn[0], qn[1], qn[2], W)) {
+        err |= ERR_NONPHYS;
+        smax_i = __longlong_as_double(0x7ff8000000000000ll);
+      } else {
+        smax_i = fabs(W.u) + W.c;
+      }
+      seg_tag = s;
+      if (i == 0) {  // one thread per domain owns its scalars
+        a.seg.t[s1 * a.seg.S + s] = t_new;
+        a.seg.smax[s2 * a.seg.S + s] = 0ull;
+        if (t_new < t_end) atomicAdd(&ctl->active[s1], 1);
+      }
+    }
+    wave_segmented_max(seg_tag, smax_i, a.seg.smax + s1 * a.seg.S);
+    __syncthreads();
+  }
+  if (err) atomicOr(&ctl->err, err);
+  if (stats) {
+    st_rs = wave_sum_u64(st_rs);
+    st_newton = wave_sum_u64(st_newton);
+    st_sweeps = wave_sum_u64(st_sweeps);
+    st_cells = wave_sum_u64(st_cells);
+    st_mlp = wave_sum_u64(st_mlp);
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&ctl->stat[0], st_rs);
+      atomicAdd(&ctl->stat[1], st_newton);
+      atomicAdd(&ctl->stat[2], st_sweeps);
+      atomicAdd(&ctl->stat[3], st_cells);
+      atomicAdd(&ctl->stat[4], st_mlp);
+    }
+  }
+}
+
+// ============================================================ advection step
+// Linear advection q_t + lambda q_x = 0, single domain, one thread per cell.
+// The predictor is the exact translation of the reconstruction, so the
+// interface state at time tau is the upwind polynomial at the foot of the
+// characteristic, and the Gauss-Legendre flux integral (exact for this degree)
+// equals lambda times the mean of that polynomial over the swept interval.
+// With the zero-mean basis phi_j of the reconstruction the mean and the point
+// value are fixed linear combinations of the coefficients per step.
+__device__ __forceinline__ void basis_at(double x, double P[4]) {
+  const double x2 = x * x;
+  P[0] = x;
+  P[1] = x2 - 1.0 / 12.0;
+  P[2] = x2 * x;
+  P[3] = x2 * x2 - 1.0 / 80.0;
+}
+// mean of phi_j over [lo, hi]
+__device__ __forceinline__ void basis_mean(double lo, double hi, double K[4]) {
+  auto prim = [](double x, double R[4]) {
+    const double x2 = x * x;
+    R[0] = 0.5 * x2;
+    R[1] = x2 * x * (1.0 / 3.0) - x * (1.0 / 12.0);
+    R[2] = 0.25 * x2 * x2;
+    R[3] = 0.2 * x2 * x2 * x - x * (1.0 / 80.0);
+  };
+  double A[4], Bv[4];
+  prim(lo, A);
+  prim(hi, Bv);
+  const double inv = 1.0 / (hi - lo);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) K[j] = (Bv[j] - A[j]) * inv;
+}
+
+template <int M>
+__device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, double vl, double vr,
+                                           double a[4]) {
+  const double DI = vr - vl, SI = vl + vr - 2.0 * qc;
+  a[0] = a[1] = a[2] = a[3] = 0.0;
+  if (M == 1) {
+    a[0] = DI;
+  } else if (M == 2) {
+    a[0] = DI;
+    a[1] = 3.0 * SI;
+  } else {
+    const double DC = qp - qm, SC = qp + qm - 2.0 * qc;
+    a[0] = 1.25 * DI - 0.125 * DC;
+    a[2] = 0.5 * DC - DI;
+    if (M == 3) {
+      a[1] = (3.0 * SI + 18.0 * SC) * (1.0 / 37.0);
+    } else {
+      a[1] = 3.75 * SI - 0.125 * SC;
+      a[3] = (5.0 / 12.0) * SC - 2.5 * SI;
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
+  Ctl *ctl = a.ctl;
+  const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
+  if (ctl->active[slot] == 0) {
+    carry_slot(a.seg, ctl, slot);
+    return;
+  }
+  const int cur = ctl->cur[slot];
+  const double *__restrict__ qin = cur ? a.q1 : a.q0;
+  double *__restrict__ qout = cur ? a.q0 : a.q1;
+  const double *__restrict__ vin = cur ? a.v1 : a.v0;
+  double *__restrict__ vout = cur ? a.v0 : a.v1;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) {
+    ctl->cur[s1] = 1 - cur;
+    ctl->steps[s1] = ctl->steps[slot] + 1;
+    ctl->active[s2] = 0;
+  }
+  const int n = a.n;
+  const double dx = a.seg.dx[0];
+  const double t = a.seg.t[slot * a.seg.S];
+  const double t_end = ctl->t_end;
+  double dt, t_new;
+  bool done;
+  domain_dt(a.cfl, dx, fabs(a.lambda), t, t_end, dt, t_new, done);
+  const double cn = a.lambda * dt / dx;  // signed Courant number
+  const bool pos = a.lambda > 0.0;
+  // per-step constants: mean of each basis function over the swept interval
+  // and its value at the foot of the characteristic
+  double Kin[4], Pin[4];
+  if (pos) {
+    basis_mean(0.5 - cn, 0.5, Kin);
+    basis_at(0.5 - cn, Pin);
+  } else {
+    basis_mean(-0.5, -0.5 - cn, Kin);
+    basis_at(-0.5 - cn, Pin);
+  }
+  for (int i = gid; i < n; i += gridDim.x * blockDim.x) {
+    if (done) {
+      qout[i] = qin[i];
+      vout[i] = vin[i];
+      if (i == n - 1) vout[n] = vin[n];
+      continue;
+    }
+    auto Q = [&](int k) -> double {
+      if (a.periodic) {
+        if (k < 0) k += n;
+        if (k >= n) k -= n;
+      } else {
+        if (k < 0) k = 0;
+        if (k >= n) k = n - 1;
+      }
+      return qin[k];
+    };
+    auto V = [&](int k) -> double {  // interface index 0..n
+      if (a.periodic) {
+        if (k < 0) k += n;
+        if (k > n) k -= n;
+      }
+      return vin[k];
+    };
+    double ac[4], au[4];
+    const double qc = qin[i];
+    adv_coeffs<M>(Q(i - 1), qc, Q(i + 1), V(i), V(i + 1), ac);
+    double mean_self = qc, pt_self = qc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mean_self += ac[j] * Kin[j];
+      pt_self += ac[j] * Pin[j];
+    }
+    double qn;
+    if (pos) {
+      // upwind neighbour i-1 supplies the left interface
+      double mean_up, pt_up;
+      if (i == 0 && !a.periodic) {  // inflow: ghost cell holding this cell's average
+        mean_up = qc;
+        pt_up = qc;
+      } else {
+        const double qu = Q(i - 1);
+        adv_coeffs<M>(Q(i - 2), qu, qc, V(i - 1), V(i), au);
+        mean_up = qu;
+        pt_up = qu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          mean_up += au[j] * Kin[j];
+          pt_up += au[j] * Pin[j];
+        }
+      }
+      qn = qc - cn * (mean_self - mean_up);
+      vout[i + 1] = pt_self;
+      if (i == 0) vout[0] = pt_up;
+    } else {
+      double mean_up, pt_up;
+      if (i == n - 1 && !a.periodic) {  // inflow from the right: ghost average
+        mean_up = qc;
+        pt_up = qc;
+      } else {
+        const double qu = Q(i + 1);
+        adv_coeffs<M>(qc, qu, Q(i + 2), V(i + 1), V(i + 2), au);
+        mean_up = qu;
+        pt_up = qu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          mean_up += au[j] * Kin[j];
+          pt_up += au[j] * Pin[j];
+        }
+      }
+      qn = qc - cn * (mean_up - mean_self);
+      vout[i] = pt_self;
+      if (i == n - 1) vout[n] = pt_up;
+    }
+    qout[i] = qn;
+    if (!isfinite(qn)) atomicOr(&ctl->err, ERR_NONPHYS);
+  }
+  if (gid == 0) {
+    a.seg.t[s1 * a.seg.S] = t_new;
+    a.seg.smax[s1 * a.seg.S] = dbits(fabs(a.lambda));
+    a.seg.smax[s2 * a.seg.S] = 0ull;
+    if (t_new < t_end) atomicAdd(&ctl->active[s1], 1);
+  }
+}
+
+// ============================================================ set-up kernels
+// First-step interface data: the Riemann solution at x/t = 0 between the left
+// (v0) and right (v1) limits of the initial condition; written into v0.
+__global__ void init_interfaces_euler(double *v0, const double *v1, int ti, Gas G, int maxit,
+                                      double tol, Ctl *ctl) {
+  unsigned err = 0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ti; k += gridDim.x * blockDim.x) {
+    double QL[3] = {v0[k], v0[ti + k], v0[2 * ti + k]};
+    double QR[3] = {v1[k], v1[ti + k], v1[2 * ti + k]};
+    RSOut o;
+    err |= interact(G, QL, QR, 0.0, 0, 0.0, nullptr, maxit, tol, o);
+    v0[k] = o.Q[0];
+    v0[ti + k] = o.Q[1];
+    v0[2 * ti + k] = o.Q[2];
+  }
+  if (err) atomicOr(&ctl->err, err);
+}
+
+__global__ void init_interfaces_adv(double *v0, const double *v1, int ti, double lambda) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ti; k += gridDim.x * blockDim.x)
+    if (lambda < 0.0) v0[k] = v1[k];
+}
+
+// S_max over each domain's cells of the state in buffer `which` into slot.
+__global__ __launch_bounds__(256) void domain_smax(const double *q, int tc, Seg seg, int slot, Gas G,
+                                                   Ctl *ctl) {
+  // cells are visited in order within a wave, so domains are non-decreasing
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < tc; base += stride) {
+    const int c = base + threadIdx.x;
+    int tag = -1;
+    double sv = 0.0;
+    if (c < tc) {
+      tag = find_domain(seg.cell_off, c, 0, seg.S - 1);
+      Prim W;
+      if (to_prim(G, q[c], q[tc + c], q[2 * tc + c], W)) {
+        sv = fabs(W.u) + W.c;
+      } else {
+        sv = __longlong_as_double(0x7ff8000000000000ll);
+        atomicOr(&ctl->err, ERR_NONPHYS);
+      }
+    }
+    wave_segmented_max(tag, sv, seg.smax + slot * seg.S);
+  }
+}
+
+// Reset the control block and domain times.
+__global__ void reset_ctl(Ctl *ctl, Seg seg, double t0, long long steps, int cur, double smax_const) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) {
+    for (int k = 0; k < 3; ++k) {
+      ctl->cur[k] = cur;
+      ctl->active[k] = 0;
+      ctl->steps[k] = steps;
+    }
+    ctl->err = 0;
+    ctl->t_end = 0.0;
+    for (int k = 0; k < 5; ++k) ctl->stat[k] = 0ull;
+  }
+  for (int s = gid; s < seg.S; s += gridDim.x * blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      seg.t[k * seg.S + s] = t0;
+      seg.smax[k * seg.S + s] = (k == 0 && smax_const > 0.0) ? dbits(smax_const) : 0ull;
+    }
+  }
+}
+
+// Before a run: set t_end and count active domains of the slot; clear the two
+// following slots.  One block.
+__global__ __launch_bounds__(256) void run_prologue(Ctl *ctl, Seg seg, int slot, double t_end) {
+  __shared__ int cnt;
+  const int s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int local = 0;
+  for (int s = threadIdx.x; s < seg.S; s += blockDim.x) {
+    if (seg.t[slot * seg.S + s] < t_end) ++local;
+    seg.smax[s1 * seg.S + s] = 0ull;
+    seg.smax[s2 * seg.S + s] = 0ull;
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ctl->t_end = t_end;
+    ctl->active[slot] = cnt;
+    ctl->active[s1] = 0;
+    ctl->active[s2] = 0;
+  }
+}
+
+// Bitwise digest of a buffer (sum and xor of the 64-bit patterns).
+__global__ void digest(const double *x, long long n, Ctl *ctl) {
+  unsigned long long s = 0, xr = 0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    unsigned long long b = dbits(x[k]);
+    s += b * 0x9E3779B97F4A7C15ull + (unsigned long long)k;
+    xr ^= b + 0x632BE59BD9B4E019ull * (unsigned long long)k;
+  }
+  s = wave_sum_u64(s);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) xr ^= __shfl_xor(xr, d, 64);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&ctl->hash[0], s);
+    atomicXor(&ctl->hash[1], xr);
+  }
+}
+
+// ============================================================ launchers
+// (host-callable wrappers so that the API file needs no kernel templates)
+template <int M, int B>
+static hipError_t launch_euler_mb(const EulerArgs<M> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((euler_step<M, B>), dim3(grid), dim3(B), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, hipStream_t st) {
+  switch (block) {
+    case 64: return launch_euler_mb<M, 64>(a, grid, st);
+    case 128: return launch_euler_mb<M, 128>(a, grid, st);
+    case 256: return launch_euler_mb<M, 256>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int M>
+hipError_t euler_occupancy(int block, int *blocks_per_cu) {
+  switch (block) {
+    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 64>, 64, 0);
+    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 128>, 128, 0);
+    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 256>, 256, 0);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int M>
+hipError_t launch_adv(const AdvArgs<M> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((adv_step<M>), dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_euler<1>(const EulerArgs<1> &, int, int, hipStream_t);
+template hipError_t launch_euler<2>(const EulerArgs<2> &, int, int, hipStream_t);
+template hipError_t launch_euler<3>(const EulerArgs<3> &, int, int, hipStream_t);
+template hipError_t euler_occupancy<1>(int, int *);
+template hipError_t euler_occupancy<2>(int, int *);
+template hipError_t euler_occupancy<3>(int, int *);
+template hipError_t launch_adv<1>(const AdvArgs<1> &, int, hipStream_t);
+template hipError_t launch_adv<2>(const AdvArgs<2> &, int, hipStream_t);
+template hipError_t launch_adv<3>(const AdvArgs<3> &, int, hipStream_t);
+template hipError_t launch_adv<4>(const AdvArgs<4> &, int, hipStream_t);
+
+hipError_t launch_init_interfaces_euler(double *v0, const double *v1, int ti, const Gas &G, int maxit,
+                                        double tol, Ctl *ctl, hipStream_t st) {
+  int grid = (ti + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(init_interfaces_euler, dim3(grid), dim3(256), 0, st, v0, v1, ti, G, maxit, tol, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_interfaces_adv(double *v0, const double *v1, int ti, double lambda,
+                                      hipStream_t st) {
+  int grid = (ti + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(init_interfaces_adv, dim3(grid), dim3(256), 0, st, v0, v1, ti, lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_domain_smax(const double *q, int tc, const Seg &seg, int slot, const Gas &G, Ctl *ctl,
+                              hipStream_t st) {
+  int grid = (tc + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(domain_smax, dim3(grid), dim3(256), 0, st, q, tc, seg, slot, G, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_ctl(Ctl *ctl, const Seg &seg, double t0, long long steps, int cur,
+                            double smax_const, hipStream_t st) {
+  int grid = (seg.S + 255) / 256;
+  if (grid < 1) grid = 1;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(reset_ctl, dim3(grid), dim3(256), 0, st, ctl, seg, t0, steps, cur, smax_const);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_prologue(Ctl *ctl, const Seg &seg, int slot, double t_end, hipStream_t st) {
+  hipLaunchKernelGGL(run_prologue, dim3(1), dim3(256), 0, st, ctl, seg, slot, t_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_digest(const double *x, long long n, Ctl *ctl, hipStream_t st) {
+  long long g = (n + 255) / 256;
+  int grid = (int)(g > 2048 ? 2048 : (g < 1 ? 1 : g));
+  hipLaunchKernelGGL(digest, dim3(grid), dim3(256), 0, st, x, n, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace grp

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs.  Bar: relative L-infinity <= 1e-11 after one step and <= 1e-9
+at t_end, per variable, for q and for the interface data."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_21911_amd import inputs as I
+
+from ._cases import acoustic_case, advection_case, network_case, oracle_cfg, rel_linf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ONE_STEP = 1e-11
+T_END = 1e-9
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_21911_amd import grprec
+    grprec.lib()
+    return grprec
+
+
+def _gpu_sim(G, system, order, cells, lengths, q, vl, vr, bc, **kw):
+    return G.Simulation(system, order, cells, lengths, q, vl, vr, bc=bc, **kw)
+
+
+# ------------------------------------------------------------- advection
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+@pytest.mark.parametrize("kind,n", [("sin2pi", 100), ("square", 64), ("sin2pi", 1027)])
+def test_advection_parity(G, order, kind, n):
+    dx, q, vl, vr = advection_case(kind, n)
+    c = oracle_cfg(oracle.ADVECTION, order, oracle.PERIODIC)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_PERIODIC)
+    try:
+        dt = sim.step(1.0, want_dt=True)
+        qo, vo, dto, _, _ = oracle.step(c, dx, q, v, 0.0, 1.0)
+        assert abs(dt - dto) <= 1e-15 * dto
+        qg, vg, t, steps = sim.numpy_state()
+        assert rel_linf(qg, qo) <= ONE_STEP
+        assert rel_linf(vg, vo) <= ONE_STEP
+        steps, t = sim.run(1.0)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 1.0)
+        qg, vg, t, steps = sim.numpy_state()
+        assert t == tr == 1.0 and steps == kr
+        assert rel_linf(qg, qr) <= T_END
+        assert rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_advection_negative_speed_transmissive(G, order):
+    n = 80
+    dx, q, vl, vr = advection_case("sin2pi", n)
+    c = oracle_cfg(oracle.ADVECTION, order, oracle.TRANSMISSIVE, lam=-0.7)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_TRANSMISSIVE,
+                   lam=-0.7)
+    try:
+        sim.run(0.3)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 0.3)
+        qg, vg, t, steps = sim.numpy_state()
+        assert steps == kr
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
+# ------------------------------------------------------------- Euler
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("block", [64, 256])
+def test_euler_density_wave_parity(G, order, block):
+    n = 300  # several tiles and a ragged tail at every block size
+    dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
+    c = oracle_cfg(oracle.EULER, order, oracle.PERIODIC)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_PERIODIC,
+                   schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=block)
+    try:
+        dt = sim.step(2.0, want_dt=True)
+        qo, vo, dto, _, _ = oracle.step(c, dx, q, v, 0.0, 2.0)
+        assert abs(dt - dto) <= 1e-14 * dto
+        qg, vg, _, _ = sim.numpy_state()
+        assert rel_linf(qg, qo) <= ONE_STEP and rel_linf(vg, vo) <= ONE_STEP
+        sim.run(0.25)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 0.25)
+        qg, vg, t, steps = sim.numpy_state()
+        assert t == tr and steps == kr
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_euler_acoustic_parity(G, order):
+    """Genuinely nonlinear smooth flow (rho, u, p all vary)."""
+    n = 130
+    dx, q, vl, vr = acoustic_case(n)
+    c = oracle_cfg(oracle.EULER, order, oracle.PERIODIC)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_PERIODIC,
+                   schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=128)
+    try:
+        sim.step(1.0)
+        qo, vo, _, _, _ = oracle.step(c, dx, q, v, 0.0, 1.0)
+        qg, vg, _, _ = sim.numpy_state()
+        assert rel_linf(qg, qo) <= ONE_STEP and rel_linf(vg, vo) <= ONE_STEP
+        sim.run(0.3)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 0.3)
+        qg, vg, t, steps = sim.numpy_state()
+        assert steps == kr
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
+@pytest.mark.parametrize("schedule", [1, 2, 3])
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_network_parity_every_schedule(G, schedule, block):
+    """Independent transmissive segments of uneven length (3 .. 400 cells):
+    every segment after 3 of its own steps equals the single-domain oracle."""
+    net = network_case(40, seed=5, nmax=400)
+    S = len(net.n_cells)
+    c = oracle_cfg(oracle.EULER, 3, oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 3)
+    sim = _gpu_sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                   G.GRPREC_BC_TRANSMISSIVE, schedule=schedule, block=block)
+    try:
+        steps, _ = sim.run(1e9, 3)
+        assert steps == 3
+        qg, vg, _, _ = sim.numpy_state()
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-14)
+        for s in range(S):
+            c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+            assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= ONE_STEP * 10, s
+            assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= ONE_STEP * 10, s
+    finally:
+        sim.close()
+
+
+def test_graph_replay_bitwise_equals_eager(G):
+    """grprec_run (captured graphs of 30 steps) == the same steps launched one by one."""
+    net = network_case(25, seed=11, nmax=300)
+    outs = []
+    for use_run in (True, False):
+        sim = _gpu_sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                       G.GRPREC_BC_TRANSMISSIVE, schedule=G.GRPREC_SCHED_PACKED, block=128)
+        try:
+            if use_run:
+                sim.run(1e9, 67)
+            else:
+                for _ in range(67):
+                    sim.step(1e9)
+            qg, vg, _, steps = sim.numpy_state()
+            assert steps == 67
+            outs.append((qg, vg))
+        finally:
+            sim.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_sod_linear_grprec_reports_failure(G):
+    """Both sides refuse the Sod tube with linear GRPrec at the first step."""
+    n = 100
+    dx, q, vl, vr = I.euler_shock_tube(n)
+    c = oracle_cfg(oracle.EULER, 3, oracle.TRANSMISSIVE)
+    v = oracle.init_interfaces(c, vl, vr)
+    with pytest.raises(oracle.OracleError):
+        oracle.step(c, dx, q, v, 0.0, 0.2)
+    sim = _gpu_sim(G, G.GRPREC_EULER, 3, [n], [1.0], q, vl, vr, G.GRPREC_BC_TRANSMISSIVE)
+    try:
+        with pytest.raises(G.GrprecError) as ei:
+            sim.step(0.2, want_dt=True)
+        assert ei.value.code in (G.GRPREC_E_PREDICTOR, G.GRPREC_E_NONPHYSICAL)
+    finally:
+        sim.close()
+
+
+# ------------------------------------------------------------- Riemann solver
+def test_riemann_batch_matches_oracle(G):
+    WL, WR = I.random_tube_states(20260223, 4000)
+    wl = torch.from_numpy(WL).cuda()
+    wr = torch.from_numpy(WR).cuda()
+    ps, it = G.grprec_riemann_batch(wl, wr)
+    ps = ps.cpu().numpy()
+    it = it.cpu().numpy()
+    n_ok = 0
+    for k in range(len(WL)):
+        rc, p_ref, it_ref = oracle.riemann_rc(1.4, WL[k], WR[k])
+        if rc == oracle.OK:
+            assert abs(ps[k] - p_ref) <= 1e-12 * p_ref, k
+            assert abs(int(it[k]) - it_ref) <= 1, k
+            n_ok += 1
+        else:
+            assert int(it[k]) == rc, (k, it[k], rc)
+    assert n_ok > 1000
