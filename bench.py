@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Throughput of the GRPrec finite-volume step on one MI355X.
+
+Workload (the headline): a network of 10,000 independent 1D Euler segments
+(gamma 1.4, FP64, order 3), cell counts log-uniform in [3, 2000] from a seed,
+lengths uniform in [0.01, 1], transmissive ends, smooth initial data
+rho = 1 + 0.1 sin(k x), u = 0.5, p = 1 with per-segment k in [1, 8].
+A step advances every segment by one of its own time steps.
+
+Forms: "plain" (the single-domain kernel launched once per segment per step),
+"batched" (one persistent launch per step over tiles of all segments, HIP
+graphs, autotuned schedule) with the PVRS Newton start, and "batched + MLP"
+(the learned star-pressure proposal, trained at start-up on the GPU).
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 cell-updates/s (Euler, order 3) plain vs batched+MLP-guess; % HBM roofline"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic FP64 operations of the order-3 Euler step (add/mul = 1, fma = 2,
+# div/sqrt/log2/exp2 = 1 each), counted from the method's arithmetic:
+F_CELL = 289     # reconstruction 51, traces 198, flux sums 18, update + S_max 19, dt 3
+F_SWEEP = 597    # one predictor sweep: 9 nodal fluxes 81, D.F 162, K^-1 W 162, update/check 192
+F_RS = 78        # one Riemann problem without its Newton iterations
+F_NEWTON = 32    # one Newton iteration on the star pressure
+BYTES_EULER = 96  # read q and V, write q and V: 2 x 2 x 3 x 8 bytes per cell-update
+BYTES_ADV = 32
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2602_21911_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, launch_units: float):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+    except Exception:
+        return None
+    if not rec or rec.get("source_digest") != src_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def timed_run(sim, steps: int, torch):
+    """grprec_run over exactly `steps` steps, timed with events on the stream
+    the kernels run on."""
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done, _ = sim.run(1e9, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert done == steps, (done, steps)
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def make_network(G, net, guess, params, schedule, block=0):
+    return G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                        bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params,
+                        schedule=schedule, block=block)
+
+
+def flops_per_launch(G, net, guess, params, schedule, block):
+    """Operation count of one step from the solver's own iteration counters
+    (an untimed run with counters on)."""
+    sim = make_network(G, net, guess, params, schedule, block)
+    try:
+        G.grprec_enable_stats(sim.h, True)
+        k = 3
+        sim.run(1e9, k)
+        st = G.grprec_get_stats(sim.h)
+    finally:
+        sim.close()
+    cells = float(net.n_cells.sum())
+    halo = st["cells_predicted"] / (k * cells)           # redundant halo predictions
+    sweeps = st["picard_sweeps"] / k / halo
+    rs = st["rs_calls"] / k
+    newton = st["newton_iters"] / k
+    flops = F_CELL * cells + F_SWEEP * sweeps + F_RS * rs + F_NEWTON * newton
+    return flops, {"sweeps_per_cell": sweeps / cells, "rs_per_cell": rs / cells,
+                   "newton_per_rs": newton / max(rs, 1.0), "halo_factor": halo,
+                   "mlp_guesses_per_step": st["mlp_guesses"] / k}
+
+
+def bench_network(args, G, torch, params):
+    from paper_2602_21911_amd import inputs as I
+    net = I.network(n_seg=args.segments, seed=I.SEED_NETWORK)
+    cells = int(net.n_cells.sum())
+    out = {"cells": cells}
+    # batched + learned guess (headline), autotuned schedule
+    sim = make_network(G, net, G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS,
+                       params, G.GRPREC_SCHED_AUTO)
+    try:
+        sched, block = G.grprec_get_schedule(sim.h)
+        sim.run(1e9, args.warmup)
+        sec, wall = timed_run(sim, args.steps, torch)
+        out["batched_mlp"] = {"rate": cells * args.steps / sec, "ms_per_step": 1e3 * sec / args.steps,
+                              "wall_s": wall, "schedule": sched, "block": block}
+    finally:
+        sim.close()
+    # batched, PVRS start
+    sim = make_network(G, net, G.GRPREC_GUESS_PVRS, None, sched, block)
+    try:
+        sim.run(1e9, args.warmup)
+        sec, wall = timed_run(sim, args.steps, torch)
+        out["batched_pvrs"] = {"rate": cells * args.steps / sec, "ms_per_step": 1e3 * sec / args.steps}
+    finally:
+        sim.close()
+    # plain: one launch per segment per step
+    sim = make_network(G, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_PER_DOMAIN, 64)
+    try:
+        sim.run(1e9, 1)
+        sec, wall = timed_run(sim, args.plain_steps, torch)
+        out["plain"] = {"rate": cells * args.plain_steps / sec,
+                        "ms_per_step": 1e3 * sec / args.plain_steps, "launches_per_step": args.segments}
+    finally:
+        sim.close()
+    fl, it = flops_per_launch(G, net, G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS,
+                              params, sched, block)
+    out["flops_per_step"] = fl
+    out["iterations"] = it
+    out["net"] = net
+    return out
+
+
+def bench_advection(G, torch, n, order=3, steps=200, warmup=20):
+    from paper_2602_21911_amd import inputs as I
+    dx, q, vl, vr = I.adv_sin2pi(n)
+    sim = G.Simulation(G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
+    try:
+        sim.run(1e9, warmup)
+        sec, _ = timed_run(sim, steps, torch)
+    finally:
+        sim.close()
+    per = sec / steps
+    gbs = BYTES_ADV * n / per / 1e9
+    return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per, "hbm_gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS}
+
+
+def bench_euler_single(G, torch, n, order=3, steps=50, warmup=5):
+    from paper_2602_21911_amd import inputs as I
+    dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
+    sim = G.Simulation(G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC,
+                       schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=256)
+    try:
+        sim.run(1e9, warmup)
+        sec, _ = timed_run(sim, steps, torch)
+    finally:
+        sim.close()
+    per = sec / steps
+    return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per,
+            "hbm_gbs": BYTES_EULER * n / per / 1e9}
+
+
+def cpu_baseline(net, steps: int):
+    """The oracle (serial C, one core) on the same network for `steps` steps."""
+    import oracle
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    S = len(net.n_cells)
+    t0 = time.perf_counter()
+    oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, steps)
+    sec = time.perf_counter() - t0
+    cells = float(net.n_cells.sum())
+    return {"value": cells * steps / sec, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {S} segments ({int(cells)} cells), {steps} steps each, serial C oracle",
+            "seconds": sec}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--segments", type=int, default=10000)
+    ap.add_argument("--train-n", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip advection / single-domain lines")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent segments would shard across GPUs with no communication).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_21911_amd import grprec as G
+    from paper_2602_21911_amd import inputs as I
+    from paper_2602_21911_amd import learn
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    G.lib()
+
+    params = None
+    mlp = None
+    if not args.no_mlp:
+        t0 = time.perf_counter()
+        ds = learn.build_dataset(args.train_n)
+        P, hist = learn.train(ds, epochs=args.epochs)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        WL, WR = I.random_tube_states(I.SEED_TUBES_HELDOUT, 100_000)
+        ev = learn.evaluate(P, torch.from_numpy(WL).cuda(), torch.from_numpy(WR).cuda())
+        params = P
+        mlp = {"train_samples": int(ds.x.shape[0]), "vacuum_dropped": ds.n_vacuum,
+               "epochs": args.epochs, "final_loss": hist[-1], "train_s": t_train, "heldout": ev}
+        log(f"mlp trained in {t_train:.1f}s, loss {hist[-1]:.3e}, held-out {ev}")
+
+    res = bench_network(args, G, torch, params)
+    net = res.pop("net")
+    cells = res["cells"]
+    head = res["batched_mlp"]
+    sec_per_step = head["ms_per_step"] / 1e3
+    flops = res["flops_per_step"]
+    bytes_step = BYTES_EULER * cells + 48.0 * len(net.n_cells)
+    achieved_tf = flops / sec_per_step / 1e12
+    traffic = traffic_from_profiles("euler_step_order3", cells)
+    roofline = {
+        "kernel": "euler_step<M=2> (fused reconstruct + predictor + Riemann + update)",
+        "bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": traffic,
+        "flops_per_launch": flops, "launch_ms": head["ms_per_step"],
+        "hbm_algorithmic_bytes_per_launch": bytes_step,
+        "hbm_gbs": bytes_step / sec_per_step / 1e9,
+        "hbm_frac": bytes_step / sec_per_step / 1e9 / PEAK_HBM_GBS,
+        "iterations": res["iterations"],
+    }
+    line = {
+        "metric": METRIC, "value": head["rate"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "network of %d independent Euler segments, order 3, cells log-uniform"
+                               " [3,2000] (seed %d), transmissive, smooth data"
+                               % (args.segments, I.SEED_NETWORK),
+                   "segments": args.segments, "total_cells": cells, "order": 3, "gamma": 1.4,
+                   "cfl": 0.9, "schedule": head["schedule"], "block": head["block"]},
+        "forms": {"plain": res["plain"], "batched_pvrs": res["batched_pvrs"], "batched_mlp": head},
+        "roofline": roofline,
+    }
+    if mlp is not None:
+        line["mlp"] = mlp
+    if not args.no_extras:
+        line["advection"] = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25)]
+        line["euler_single_domain"] = bench_euler_single(G, torch, 1 << 22)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
