@@ -201,6 +201,35 @@ def cpu_baseline(net, steps: int):
             "seconds": sec}
 
 
+def counters_run(G, torch, I):
+    """Short fixed workload for rocprofv3 --pmc passes: 3 network steps (flat
+    tiles, 64-wide blocks), 3 advection steps on 2^25 cells, and a 256 MiB
+    device copy used to calibrate the byte counters."""
+    net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
+    sim = make_network(G, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_FLAT_TILES, 64)
+    try:
+        for _ in range(3):
+            sim.step(1e9)
+        torch.cuda.synchronize()
+    finally:
+        sim.close()
+    dx, q, vl, vr = I.adv_sin2pi(1 << 25)
+    sim = G.Simulation(G.GRPREC_ADVECTION, 3, [1 << 25], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
+    try:
+        for _ in range(3):
+            sim.step(1e9)
+        torch.cuda.synchronize()
+    finally:
+        sim.close()
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": "done", "network_cells": int(net.n_cells.sum()),
+                      "advection_cells": 1 << 25, "copy_bytes": a.numel() * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +243,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip advection / single-domain lines")
+    ap.add_argument("--only", choices=["all", "advection", "counters"], default="all",
+                    help="advection: only the advection lines; counters: a short fixed run for"
+                         " hardware-counter passes (network, advection 2^25, a 256 MB copy)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -230,6 +262,13 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     G.lib()
+    if args.only == "advection":
+        out = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25)]
+        print(json.dumps({"advection": out}), flush=True)
+        return
+    if args.only == "counters":
+        counters_run(G, torch, I)
+        return
 
     params = None
     mlp = None
