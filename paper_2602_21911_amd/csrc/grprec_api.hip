@@ -25,123 +25,7 @@ hipError_t launch_reset_ctl(Ctl *, const Seg &, double, long long, int, double, 
 hipError_t launch_run_prologue(Ctl *, const Seg &, int, double, hipStream_t);
 hipError_t launch_digest(const double *, long long, Ctl *, hipStream_t);
 
-// ------------------------------------------------------------ quadrature
-// Gauss-Legendre nodes and weights on [0,1] from their closed forms (n <= 5).
-static void gl_nodes(int n, double *x, double *w) {
-  std::vector<double> xs, ws;  // on [-1,1], ascending
-  switch (n) {
-    case 1: xs = {0.0}; ws = {2.0}; break;
-    case 2: {
-      double a = 1.0 / std::sqrt(3.0);
-      xs = {-a, a}; ws = {1.0, 1.0};
-      break;
-    }
-    case 3: {
-      double a = std::sqrt(0.6);
-      xs = {-a, 0.0, a}; ws = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
-      break;
-    }
-    case 4: {
-      double r = 2.0 / 7.0 * std::sqrt(6.0 / 5.0);
-      double xi = std::sqrt(3.0 / 7.0 - r), xo = std::sqrt(3.0 / 7.0 + r);
-      double wi = (18.0 + std::sqrt(30.0)) / 36.0, wo = (18.0 - std::sqrt(30.0)) / 36.0;
-      xs = {-xo, -xi, xi, xo}; ws = {wo, wi, wi, wo};
-      break;
-    }
-    default: {
-      double r = 2.0 * std::sqrt(10.0 / 7.0);
-      double xi = std::sqrt(5.0 - r) / 3.0, xo = std::sqrt(5.0 + r) / 3.0;
-      double wi = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0, wo = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
-      xs = {-xo, -xi, 0.0, xi, xo}; ws = {wo, wi, 128.0 / 225.0, wi, wo};
-      break;
-    }
-  }
-  for (int k = 0; k < n; ++k) {
-    x[k] = 0.5 * (xs[k] + 1.0);
-    w[k] = 0.5 * ws[k];
-  }
-}
 
-// Lagrange polynomial l_k on nodes g (value, derivative) at t.
-static double lag(int n, const double *g, int k, double t) {
-  double v = 1.0;
-  for (int j = 0; j < n; ++j)
-    if (j != k) v *= (t - g[j]) / (g[k] - g[j]);
-  return v;
-}
-static double lag_d(int n, const double *g, int k, double t) {
-  // derivative by the product rule: sum over the dropped factor
-  double s = 0.0;
-  for (int j = 0; j < n; ++j) {
-    if (j == k) continue;
-    double prod = 1.0 / (g[k] - g[j]);
-    for (int l = 0; l < n; ++l)
-      if (l != k && l != j) prod *= (t - g[l]) / (g[k] - g[l]);
-    s += prod;
-  }
-  return s;
-}
-
-// Space-time predictor constants for degree M: the time matrix
-// K[b][l] = l_b(1) l_l(1) - int_0^1 l_b' l_l (Gauss-Legendre at the nodes is
-// exact for it: = l_b(1) l_l(1) - w_l l_b'(g_l)), inverted by Gauss-Jordan.
-template <int M>
-static bool st_constants(StConst<M> &C) {
-  constexpr int n = M + 1;
-  double g[5], w[5];
-  gl_nodes(n, g, w);
-  double K[n][2 * n];
-  for (int b = 0; b < n; ++b) {
-    for (int l = 0; l < n; ++l) {
-      K[b][l] = lag(n, g, b, 1.0) * lag(n, g, l, 1.0) - w[l] * lag_d(n, g, b, g[l]);
-      K[b][n + l] = (b == l) ? 1.0 : 0.0;
-    }
-  }
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < n; ++r)
-      if (std::fabs(K[r][col]) > std::fabs(K[piv][col])) piv = r;
-    if (std::fabs(K[piv][col]) < 1e-300) return false;
-    for (int k = 0; k < 2 * n; ++k) std::swap(K[col][k], K[piv][k]);
-    double d = K[col][col];
-    for (int k = 0; k < 2 * n; ++k) K[col][k] /= d;
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      double f = K[r][col];
-      for (int k = 0; k < 2 * n; ++k) K[r][k] -= f * K[col][k];
-    }
-  }
-  for (int b = 0; b < n; ++b)
-    for (int l = 0; l < n; ++l) C.KW[b][l] = K[b][n + l] * w[l];
-  for (int a = 0; a < n; ++a) {
-    for (int k = 0; k < n; ++k) C.D[a][k] = lag_d(n, g, k, g[a]);
-    C.l0[a] = lag(n, g, a, 0.0);
-    C.l1[a] = lag(n, g, a, 1.0);
-    C.w[a] = w[a];
-    double xi = g[a] - 0.5, x2 = xi * xi;
-    C.phi[a][0] = xi;
-    C.phi[a][1] = x2 - 1.0 / 12.0;
-    C.phi[a][2] = x2 * xi;
-    C.phi[a][3] = x2 * x2 - 1.0 / 80.0;
-  }
-  return true;
-}
-
-static Gas make_gas(double g) {
-  Gas G;
-  G.g = g;
-  G.gm1 = g - 1.0;
-  G.gp1 = g + 1.0;
-  G.z = (g - 1.0) / (2.0 * g);
-  G.inv_g = 1.0 / g;
-  G.two_gm1 = 2.0 / (g - 1.0);
-  G.two_gp1 = 2.0 / (g + 1.0);
-  G.gm1_gp1 = (g - 1.0) / (g + 1.0);
-  G.twog_gm1 = 2.0 * g / (g - 1.0);
-  G.gp1_2g = (g + 1.0) / (2.0 * g);
-  G.inv_gm1 = 1.0 / (g - 1.0);
-  return G;
-}
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -214,9 +98,6 @@ struct grprec_handle {
   hipStream_t stream, cap_stream;
   int slot;
   Gas gas;
-  StConst<1> C1;
-  StConst<2> C2;
-  StConst<3> C3;
   Harvest hv;
   Ctl *host_ctl;  // pinned read-back
   double *host_buf;
@@ -339,7 +220,7 @@ static int apply_schedule(grprec_handle *h, int schedule, int block) {
 
 // ------------------------------------------------------------ launches
 template <int M>
-static EulerArgs<M> euler_args(const grprec_handle *h, int slot, const StConst<M> &C) {
+static EulerArgs<M> euler_args(const grprec_handle *h, int slot) {
   EulerArgs<M> a;
   a.q0 = h->q0; a.q1 = h->q1; a.v0 = h->v0; a.v1 = h->v1;
   a.tc = (int)h->tc; a.ti = (int)h->ti;
@@ -359,7 +240,6 @@ static EulerArgs<M> euler_args(const grprec_handle *h, int slot, const StConst<M
   a.gate = h->p.mlp_gate;
   a.mlp = h->mlp;
   a.hv = h->hv;
-  a.C = C;
   return a;
 }
 
@@ -378,8 +258,8 @@ static AdvArgs<M> adv_args(const grprec_handle *h, int slot) {
 }
 
 template <int M>
-static hipError_t launch_per_domain(grprec_handle *h, int slot, const StConst<M> &C, hipStream_t st) {
-  EulerArgs<M> a = euler_args<M>(h, slot, C);
+static hipError_t launch_per_domain(grprec_handle *h, int slot, hipStream_t st) {
+  EulerArgs<M> a = euler_args<M>(h, slot);
   for (int s = 0; s < h->S; ++s) {
     const int t0 = h->dom_tile0[s], nt = h->dom_tile0[s + 1] - t0;
     a.tiles = h->tiles + t0;
@@ -393,16 +273,16 @@ static hipError_t launch_per_domain(grprec_handle *h, int slot, const StConst<M>
 static hipError_t launch_step(grprec_handle *h, int slot, hipStream_t st) {
   if (h->p.system == GRPREC_EULER && h->schedule == GRPREC_SCHED_PER_DOMAIN) {
     switch (h->M) {
-      case 1: return launch_per_domain<1>(h, slot, h->C1, st);
-      case 2: return launch_per_domain<2>(h, slot, h->C2, st);
-      default: return launch_per_domain<3>(h, slot, h->C3, st);
+      case 1: return launch_per_domain<1>(h, slot, st);
+      case 2: return launch_per_domain<2>(h, slot, st);
+      default: return launch_per_domain<3>(h, slot, st);
     }
   }
   if (h->p.system == GRPREC_EULER) {
     switch (h->M) {
-      case 1: return launch_euler<1>(euler_args<1>(h, slot, h->C1), h->block, h->grid, st);
-      case 2: return launch_euler<2>(euler_args<2>(h, slot, h->C2), h->block, h->grid, st);
-      default: return launch_euler<3>(euler_args<3>(h, slot, h->C3), h->block, h->grid, st);
+      case 1: return launch_euler<1>(euler_args<1>(h, slot), h->block, h->grid, st);
+      case 2: return launch_euler<2>(euler_args<2>(h, slot), h->block, h->grid, st);
+      default: return launch_euler<3>(euler_args<3>(h, slot), h->block, h->grid, st);
     }
   }
   long long g = (h->tc + 255) / 256;
@@ -573,9 +453,6 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(GRPREC_E_HIP);
 
-  if (h->M == 1) st_constants<1>(h->C1);
-  if (h->M == 2) st_constants<2>(h->C2);
-  if (h->M == 3) st_constants<3>(h->C3);
 
   h->cell_off.resize(h->S + 1);
   h->dx.resize(h->S);

@@ -44,47 +44,115 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------- Euler physics
+// 1/x from the hardware estimate refined by two Newton steps (within a few ulp
+// of the correctly rounded value; x > 0 finite).
+__device__ __forceinline__ double rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 // Conserved Q = (rho, rho u, E), ideal gas p = (g-1)(E - rho u^2 / 2).
 __device__ __forceinline__ void euler_flux(const Gas &G, double r, double m, double E, double &f0,
                                            double &f1, double &f2) {
-  double u = m / r;
+  double u = m * rcp(r);
   double p = G.gm1 * (E - 0.5 * m * u);
   f0 = m;
   f1 = m * u + p;
   f2 = u * (E + p);
 }
 
-// Star-region pressure function of one side and its derivative (shock branch
-// from the Rankine-Hugoniot conditions, rarefaction branch from the isentropic
-// relation and the generalised Riemann invariant).
-__device__ __forceinline__ void side_function(const Gas &G, double p, double rk, double pk, double ck,
-                                              double &f, double &fd) {
-  if (p <= pk) {
-    double pr = p / pk;
-    double pw = powpos(pr, G.z);
-    f = G.two_gm1 * ck * (pw - 1.0);
-    fd = pw / (pr * rk * ck);
-  } else {
-    double ak = G.two_gp1 / rk;
-    double bk = G.gm1_gp1 * pk;
-    double s = sqrt(ak / (bk + p));
-    f = (p - pk) * s;
-    fd = (1.0 - 0.5 * (p - pk) / (bk + p)) * s;
-  }
-}
-
 struct Prim {
   double r, u, p, c;
+  double ir, ip, ic;  // 1/r, 1/p, 1/c
 };
 
 // Primitive state and sound speed; false if not physical.
 __device__ __forceinline__ bool to_prim(const Gas &G, double r, double m, double E, Prim &w) {
   w.r = r;
-  w.u = m / r;
+  w.ir = rcp(r);
+  w.u = m * w.ir;
   w.p = G.gm1 * (E - 0.5 * m * w.u);
   bool ok = (r > 0.0) && (w.p > 0.0) && isfinite(w.u) && isfinite(w.p);
-  w.c = ok ? sqrt(G.g * w.p / r) : 0.0;
+  w.ip = ok ? rcp(w.p) : 0.0;
+  w.c = ok ? sqrt(G.g * w.p * w.ir) : 0.0;
+  w.ic = ok ? rcp(w.c) : 0.0;
   return ok;
+}
+
+// Prim from primitive values (r, p > 0 checked by the caller).
+__device__ __forceinline__ void prim_from(const Gas &G, double r, double u, double p, Prim &w) {
+  w.r = r;
+  w.u = u;
+  w.p = p;
+  w.ir = rcp(r);
+  w.ip = rcp(p);
+  w.c = sqrt(G.g * p * w.ir);
+  w.ic = rcp(w.c);
+}
+
+// y^k for a small non-negative integer k (binary powering).
+__device__ __forceinline__ double ipow(double y, int k) {
+  double r = 1.0;
+  while (k > 0) {
+    if (k & 1) r *= y;
+    y *= y;
+    k >>= 1;
+  }
+  return r;
+}
+
+// x^z, z = (g-1)/(2g), for x > 0.  When 1/z = n is an integer (n = 7 for
+// g = 1.4) the n-th root starts from a float estimate and takes two Newton
+// steps on y^n = x (each squares the relative error: 1e-7 -> 1e-14 -> 1e-28);
+// otherwise 2^(z log2 x).
+__device__ __forceinline__ double pow_z(const Gas &G, double x) {
+  if (G.root_n > 0 && x > 1e-30 && x < 1e30) {
+    const float xf = (float)x;
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * G.inv_nf);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double yn1 = ipow(y, G.root_n - 1);
+      y = fma(G.nm1_n, y, x * rcp(yn1) * G.inv_n);
+    }
+    return y;
+  }
+  return powpos(x, G.z);
+}
+
+// (p/pK)^(1/g) from w = (p/pK)^z: w^(2/(g-1)).
+__device__ __forceinline__ double dens_pow(const Gas &G, double w) {
+  return G.dens_k > 0 ? ipow(w, G.dens_k) : powpos(w, G.two_gm1);
+}
+
+// Star-region pressure function of one side, its derivative and, on the
+// rarefaction branch, w = (p/pK)^z (shock branch from the Rankine-Hugoniot
+// conditions, rarefaction branch from the isentropic relation and the
+// generalised Riemann invariant).  ip = 1/p.
+struct Side {
+  double f, fd, w;
+  bool rare;
+};
+
+__device__ __forceinline__ void side_eval(const Gas &G, double p, double ip, const Prim &K, Side &s) {
+  if (p <= K.p) {
+    s.rare = true;
+    s.w = pow_z(G, p * K.ip);
+    s.f = G.two_gm1 * K.c * (s.w - 1.0);
+    // (p/pK)^(-(g+1)/(2g)) / (rhoK cK) = w (pK / p) / (rhoK cK)
+    s.fd = s.w * K.p * ip * K.ir * K.ic;
+  } else {
+    s.rare = false;
+    s.w = 0.0;
+    const double ak = G.two_gp1 * K.ir;
+    const double bk = G.gm1_gp1 * K.p;
+    const double ibp = rcp(bk + p);
+    const double sq = sqrt(ak * ibp);
+    s.f = (p - K.p) * sq;
+    s.fd = (1.0 - 0.5 * (p - K.p) * ibp) * sq;
+  }
 }
 
 __device__ __forceinline__ double pvrs(const Prim &L, const Prim &R) {
@@ -95,82 +163,92 @@ __device__ __forceinline__ double pvrs(const Prim &L, const Prim &R) {
 
 // Newton iteration for the star pressure from p0 > 0; non-positive iterates
 // are replaced by half the previous one; stop on relative change <= tol after
-// at least one iteration.  Returns the iteration count (maxit+1 = no convergence).
+// at least one iteration.  Returns the iteration count (maxit+1 = no
+// convergence).  f_K and w_K at the final pressure come from the last
+// evaluation by a first-order correction: at convergence the step is at most
+// tol p, so the neglected term is O(tol^2) relative.
 __device__ __forceinline__ int newton_pstar(const Gas &G, const Prim &L, const Prim &R, double p,
-                                            int maxit, double tol, double &pstar, double &ustar) {
+                                            int maxit, double tol, double &pstar, double &ustar,
+                                            Side &sl, Side &sr) {
   const double du = R.u - L.u;
+  double pe = p;
   int k = 1;
   bool conv = false;
   for (; k <= maxit; ++k) {
-    double fl, fld, fr, frd;
-    side_function(G, p, L.r, L.p, L.c, fl, fld);
-    side_function(G, p, R.r, R.p, R.c, fr, frd);
-    double pn = p - (fl + fr + du) / (fld + frd);
+    pe = p;
+    const double ip = rcp(p);
+    side_eval(G, p, ip, L, sl);
+    side_eval(G, p, ip, R, sr);
+    double pn = p - (sl.f + sr.f + du) * rcp(sl.fd + sr.fd);
     if (pn <= 0.0) pn = 0.5 * p;
-    double change = 2.0 * fabs(pn - p) / (pn + p);
+    const bool stop = 2.0 * fabs(pn - p) <= tol * (pn + p);
     p = pn;
-    if (change <= tol) {
+    if (stop) {
       conv = true;
       break;
     }
   }
-  double fl, fld, fr, frd;
-  side_function(G, p, L.r, L.p, L.c, fl, fld);
-  side_function(G, p, R.r, R.p, R.c, fr, frd);
+  const double dp = p - pe;
+  sl.f = fma(sl.fd, dp, sl.f);
+  sr.f = fma(sr.fd, dp, sr.f);
+  const double rel = G.z * dp * rcp(pe);
+  sl.w = fma(sl.w, rel, sl.w);
+  sr.w = fma(sr.w, rel, sr.w);
   pstar = p;
-  ustar = 0.5 * (L.u + R.u) + 0.5 * (fr - fl);
+  ustar = 0.5 * (L.u + R.u) + 0.5 * (sr.f - sl.f);
   return conv ? k : maxit + 1;
 }
 
 // State of the exact Riemann solution on the line x/t = 0 (primitive).
 __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, const Prim &R, double ps,
-                                               double us, double &r, double &u, double &p) {
+                                               double us, const Side &sl, const Side &sr, double &r,
+                                               double &u, double &p) {
   if (us >= 0.0) {
     if (ps <= L.p) {  // left rarefaction
       if (L.u - L.c >= 0.0) {
         r = L.r; u = L.u; p = L.p;
       } else {
-        double prat = ps / L.p;
-        double cs = L.c * powpos(prat, G.z);
+        const double w = sl.rare ? sl.w : pow_z(G, ps * L.ip);
+        const double cs = L.c * w;
         if (us - cs < 0.0) {
-          r = L.r * powpos(prat, G.inv_g); u = us; p = ps;
+          r = L.r * dens_pow(G, w); u = us; p = ps;
         } else {  // fan: u - c = 0 and u + 2c/(g-1) is carried from the left
-          double c = G.two_gp1 * (L.c + 0.5 * G.gm1 * L.u);
-          double cr = c / L.c;
+          const double c = G.two_gp1 * (L.c + 0.5 * G.gm1 * L.u);
+          const double cr = c * L.ic;
           r = L.r * powpos(cr, G.two_gm1);
           u = c;
           p = L.p * powpos(cr, G.twog_gm1);
         }
       }
     } else {  // left shock
-      double pm = ps / L.p;
-      double s = L.u - L.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
+      const double pm = ps * L.ip;
+      const double s = L.u - L.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
       if (s >= 0.0) {
         r = L.r; u = L.u; p = L.p;
       } else {
-        r = L.r * (pm + G.gm1_gp1) / (pm * G.gm1_gp1 + 1.0); u = us; p = ps;
+        r = L.r * (pm + G.gm1_gp1) * rcp(pm * G.gm1_gp1 + 1.0); u = us; p = ps;
       }
     }
   } else {
     if (ps > R.p) {  // right shock
-      double pm = ps / R.p;
-      double s = R.u + R.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
+      const double pm = ps * R.ip;
+      const double s = R.u + R.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
       if (s <= 0.0) {
         r = R.r; u = R.u; p = R.p;
       } else {
-        r = R.r * (pm + G.gm1_gp1) / (pm * G.gm1_gp1 + 1.0); u = us; p = ps;
+        r = R.r * (pm + G.gm1_gp1) * rcp(pm * G.gm1_gp1 + 1.0); u = us; p = ps;
       }
     } else {  // right rarefaction
       if (R.u + R.c <= 0.0) {
         r = R.r; u = R.u; p = R.p;
       } else {
-        double prat = ps / R.p;
-        double cs = R.c * powpos(prat, G.z);
+        const double w = sr.rare ? sr.w : pow_z(G, ps * R.ip);
+        const double cs = R.c * w;
         if (us + cs >= 0.0) {
-          r = R.r * powpos(prat, G.inv_g); u = us; p = ps;
+          r = R.r * dens_pow(G, w); u = us; p = ps;
         } else {  // fan: u + c = 0 and u - 2c/(g-1) is carried from the right
-          double c = G.two_gp1 * (R.c - 0.5 * G.gm1 * R.u);
-          double cr = c / R.c;
+          const double c = G.two_gp1 * (R.c - 0.5 * G.gm1 * R.u);
+          const double cr = c * R.ic;
           r = R.r * powpos(cr, G.two_gm1);
           u = -c;
           p = R.p * powpos(cr, G.twog_gm1);
@@ -235,11 +313,11 @@ __device__ __forceinline__ double start_pressure(const Gas &G, const Prim &L, co
   used_mlp = false;
   double pv = pvrs(L, R);
   if (guess == 1 && mlp != nullptr) {
-    double pbar = 0.5 * (L.p + R.p);
-    double rbar = 0.5 * (L.r + R.r);
-    double cbar = sqrt(G.g * pbar / rbar);
-    double jump = fabs(R.p - L.p) / pbar + fabs(R.r - L.r) / rbar + fabs(R.u - L.u) / cbar;
-    if (gate < 0.0 || jump > gate) {
+    // relative jump |dp|/pbar + |drho|/rhobar + |du|/cbar > gate, without divisions
+    const double pbar = 0.5 * (L.p + R.p), rbar = 0.5 * (L.r + R.r), cbar = 0.5 * (L.c + R.c);
+    const double lhs = fabs(R.p - L.p) * rbar * cbar + fabs(R.r - L.r) * pbar * cbar +
+                       fabs(R.u - L.u) * pbar * rbar;
+    if (gate < 0.0 || lhs > gate * pbar * rbar * cbar) {
       float x[6];
       double pb;
       mlp_features(G, L, R, x, pb);
@@ -287,11 +365,12 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
   }
   double p0 = pguess > 0.0 ? pguess : start_pressure(G, L, R, guess, gate, mlp, o.mlp);
   double ps, us;
-  int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us);
+  Side sl, sr;
+  int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us, sl, sr);
   o.iters = it;
   o.pstar = ps;
   double r, u, p;
-  sample_at_zero(G, L, R, ps, us, r, u, p);
+  sample_at_zero(G, L, R, ps, us, sl, sr, r, u, p);
   double E = p * G.inv_gm1 + 0.5 * r * u * u;
   o.Q[0] = r;
   o.Q[1] = r * u;

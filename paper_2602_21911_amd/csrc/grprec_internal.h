@@ -35,19 +35,43 @@ struct Gas {
   double twog_gm1; // 2g/(g-1)
   double gp1_2g;   // (g+1)/(2g)
   double inv_gm1;  // 1/(g-1)
+  int root_n;      // 1/z when it is an integer (7 for g = 1.4), else 0
+  int dens_k;      // 2/(g-1) when it is an integer (5 for g = 1.4), else 0
+  double inv_n, nm1_n;  // 1/root_n, (root_n - 1)/root_n
+  float inv_nf;
 };
 
-// Per-degree constants of the space-time predictor and of the reconstruction.
-// Nodes g_a are the (M+1)-point Gauss-Legendre points on [0,1].
-template <int M>
-struct StConst {
-  double D[M + 1][M + 1];   // D[a][k] = l_k'(g_a)
-  double KW[M + 1][M + 1];  // K^{-1} diag(w), K the time matrix of the weak form
-  double l0[M + 1];         // l_a(0)
-  double l1[M + 1];         // l_a(1)
-  double w[M + 1];          // Gauss-Legendre weights on [0,1]
-  double phi[M + 1][4];     // zero-mean basis xi, xi^2-1/12, xi^3, xi^4-1/80 at xi = g_a - 1/2
-};
+namespace gasc {
+constexpr double cabs(double x) { return x < 0.0 ? -x : x; }
+constexpr double cround(double x) { return (double)(long long)(x + 0.5); }
+}  // namespace gasc
+
+// Ideal-gas constants from gamma (usable at compile time).
+constexpr Gas make_gas(double g) {
+  Gas G{};
+  G.g = g;
+  G.gm1 = g - 1.0;
+  G.gp1 = g + 1.0;
+  G.z = (g - 1.0) / (2.0 * g);
+  G.inv_g = 1.0 / g;
+  G.two_gm1 = 2.0 / (g - 1.0);
+  G.two_gp1 = 2.0 / (g + 1.0);
+  G.gm1_gp1 = (g - 1.0) / (g + 1.0);
+  G.twog_gm1 = 2.0 * g / (g - 1.0);
+  G.gp1_2g = (g + 1.0) / (2.0 * g);
+  G.inv_gm1 = 1.0 / (g - 1.0);
+  const double n = 2.0 * g / (g - 1.0), k = 2.0 / (g - 1.0);
+  G.root_n = (n < 32.0 && gasc::cabs(n - gasc::cround(n)) < 1e-9) ? (int)gasc::cround(n) : 0;
+  G.dens_k = (k < 32.0 && gasc::cabs(k - gasc::cround(k)) < 1e-9) ? (int)gasc::cround(k) : 0;
+  G.inv_n = G.root_n ? 1.0 / G.root_n : 0.0;
+  G.nm1_n = G.root_n ? (G.root_n - 1.0) / G.root_n : 0.0;
+  G.inv_nf = (float)G.inv_n;
+  return G;
+}
+
+// Diatomic ideal gas, gamma = 1.4: the kernels carry a compile-time copy.
+constexpr double kGammaAir = 1.4;
+constexpr Gas kAir = make_gas(kGammaAir);
 
 // Domain (segment) tables in the workspace.
 struct Seg {
@@ -84,7 +108,6 @@ struct EulerArgs {
   double gate;
   const float *mlp;
   Harvest hv;
-  StConst<M> C;
 };
 
 template <int M>

@@ -11,6 +11,7 @@
 
 #include "grprec_device.h"
 #include "grprec_internal.h"
+#include "grprec_tables.h"
 
 namespace grp {
 
@@ -60,11 +61,29 @@ __device__ __forceinline__ int find_domain(const int *cell_off, int c, int lo, i
   return lo;
 }
 
+// Element b of a small compile-time array with a uniform runtime index,
+// as a chain of selects (no memory).
+template <int N>
+__device__ __forceinline__ double pick(const double (&t)[N], int b) {
+  double r = t[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = (b == k) ? t[k] : r;
+  return r;
+}
+
 // ============================================================ Euler step
-template <int M, int B>
-__global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
+// Waves per SIMD the register allocation must leave room for (1 = no limit).
+#ifndef GRPREC_EULER_WAVES
+#define GRPREC_EULER_WAVES 1
+#endif
+
+// AIR: gamma is 1.4 and the gas constants are compile-time values.
+template <int M, int B, bool AIR>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES)))
+void euler_step(EulerArgs<M> a) {
   constexpr int N = M + 1;   // nodes per direction
   constexpr int NT = M + 2;  // trace times: N Gauss-Legendre times and tau = 1
+  constexpr tab::Predictor<M> T = tab::predictor<M>();
   __shared__ double sTL[3 * NT][B];
   __shared__ double sTR[3 * NT][B];
   __shared__ double sF[3][B];
@@ -88,7 +107,7 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
   }
   const double t_end = ctl->t_end;
   const bool stats = ctl->stats_on != 0;
-  const Gas &G = a.gas;
+  const Gas G = AIR ? kAir : a.gas;
   const int e = threadIdx.x;
   const int tc = a.tc, ti = a.ti;
   unsigned err = 0;
@@ -173,8 +192,8 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
         }
 #pragma unroll
         for (int k = 0; k < N; ++k)
-          w[v][k] = qc + a1 * a.C.phi[k][0] + a2 * a.C.phi[k][1] + a3 * a.C.phi[k][2] +
-                    a4 * a.C.phi[k][3];
+          w[v][k] = qc + a1 * T.phi[k][0] + a2 * T.phi[k][1] + a3 * T.phi[k][2] +
+                    a4 * T.phi[k][3];
       }
       // Picard iteration of the space-time Galerkin equations
       double qh[3][N][N];
@@ -203,22 +222,23 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
             for (int l = 0; l < N; ++l) {
               double acc = 0.0;
 #pragma unroll
-              for (int k = 0; k < N; ++k) acc += a.C.D[x][k] * F[v][k][l];
+              for (int k = 0; k < N; ++k) acc += T.D[x][k] * F[v][k][l];
               Gd[l] = acc;
             }
 #pragma unroll
             for (int b = 0; b < N; ++b) {
               double acc = 0.0;
 #pragma unroll
-              for (int l = 0; l < N; ++l) acc += a.C.KW[b][l] * Gd[l];
+              for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[l];
               const double nv = w[v][x] - nu * acc;
-              diff = nanmax(diff, fabs(nv - qh[v][x][b]));
+              // non-finite values do not stop the sweep here: they reach the
+              // traces and are caught by the physical-state checks
+              diff = fmax(diff, fabs(nv - qh[v][x][b]));
               nrm = fmax(nrm, fabs(nv));
               qh[v][x][b] = nv;
             }
           }
         }
-        if (diff != diff) break;
         if (diff <= a.picard_tol * (1.0 + nrm)) {
           conv = true;
           break;
@@ -236,8 +256,8 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
           double l = 0.0, r = 0.0;
 #pragma unroll
           for (int x = 0; x < N; ++x) {
-            l += a.C.l0[x] * qh[v][x][b];
-            r += a.C.l1[x] * qh[v][x][b];
+            l += T.l0[x] * qh[v][x][b];
+            r += T.l1[x] * qh[v][x][b];
           }
           sTL[v * NT + b][e] = l;
           sTR[v * NT + b][e] = r;
@@ -246,9 +266,9 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
         for (int x = 0; x < N; ++x) {
           double at1 = 0.0;
 #pragma unroll
-          for (int b = 0; b < N; ++b) at1 += a.C.l1[b] * qh[v][x][b];
-          l1sum += a.C.l0[x] * at1;
-          r1sum += a.C.l1[x] * at1;
+          for (int b = 0; b < N; ++b) at1 += T.l1[b] * qh[v][x][b];
+          l1sum += T.l0[x] * at1;
+          r1sum += T.l1[x] * at1;
         }
         sTL[v * NT + N][e] = l1sum;
         sTR[v * NT + N][e] = r1sum;
@@ -297,7 +317,7 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
           for (int v = 0; v < 3; ++v) { f[v] = o.F[v]; qs[v] = o.Q[v]; }
         }
         if (b < N) {
-          const double wb = a.C.w[b];
+          const double wb = pick<N>(T.w, b);
 #pragma unroll
           for (int v = 0; v < 3; ++v) FR[v] += wb * f[v];
         } else {
@@ -326,7 +346,7 @@ __global__ __launch_bounds__(B) void euler_step(EulerArgs<M> a) {
         st_newton += o.iters;
         st_mlp += o.mlp ? 1 : 0;
         if (b < N) {
-          const double wb = a.C.w[b];
+          const double wb = pick<N>(T.w, b);
 #pragma unroll
           for (int v = 0; v < 3; ++v) FL[v] += wb * o.F[v];
         } else {
@@ -692,7 +712,10 @@ __global__ void digest(const double *x, long long n, Ctl *ctl) {
 // (host-callable wrappers so that the API file needs no kernel templates)
 template <int M, int B>
 static hipError_t launch_euler_mb(const EulerArgs<M> &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((euler_step<M, B>), dim3(grid), dim3(B), 0, st, a);
+  if (a.gas.g == kGammaAir)
+    hipLaunchKernelGGL((euler_step<M, B, true>), dim3(grid), dim3(B), 0, st, a);
+  else
+    hipLaunchKernelGGL((euler_step<M, B, false>), dim3(grid), dim3(B), 0, st, a);
   return hipGetLastError();
 }
 
@@ -709,9 +732,9 @@ hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, hipStream_t 
 template <int M>
 hipError_t euler_occupancy(int block, int *blocks_per_cu) {
   switch (block) {
-    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 64>, 64, 0);
-    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 128>, 128, 0);
-    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 256>, 256, 0);
+    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 64, true>, 64, 0);
+    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 128, true>, 128, 0);
+    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 256, true>, 256, 0);
     default: return hipErrorInvalidValue;
   }
 }

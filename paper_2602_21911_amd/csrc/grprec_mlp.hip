@@ -13,21 +13,7 @@ using namespace grp;
 
 namespace {
 
-Gas gas_of(double g) {
-  Gas G;
-  G.g = g;
-  G.gm1 = g - 1.0;
-  G.gp1 = g + 1.0;
-  G.z = (g - 1.0) / (2.0 * g);
-  G.inv_g = 1.0 / g;
-  G.two_gm1 = 2.0 / (g - 1.0);
-  G.two_gp1 = 2.0 / (g + 1.0);
-  G.gm1_gp1 = (g - 1.0) / (g + 1.0);
-  G.twog_gm1 = 2.0 * g / (g - 1.0);
-  G.gp1_2g = (g + 1.0) / (2.0 * g);
-  G.inv_gm1 = 1.0 / (g - 1.0);
-  return G;
-}
+Gas gas_of(double g) { return make_gas(g); }
 
 int grid_for(long long n, int block, int cap) {
   long long g = (n + block - 1) / block;
@@ -41,24 +27,26 @@ __global__ void riemann_batch_kernel(const double *wl, const double *wr, long lo
                                      int *iters) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    Prim L, R;
-    L.r = wl[3 * i]; L.u = wl[3 * i + 1]; L.p = wl[3 * i + 2];
-    R.r = wr[3 * i]; R.u = wr[3 * i + 1]; R.p = wr[3 * i + 2];
-    bool ok = L.r > 0.0 && R.r > 0.0 && L.p > 0.0 && R.p > 0.0 && isfinite(L.u) && isfinite(R.u);
+    const double rl = wl[3 * i], ul = wl[3 * i + 1], pl = wl[3 * i + 2];
+    const double rr = wr[3 * i], ur = wr[3 * i + 1], pr = wr[3 * i + 2];
+    bool ok = rl > 0.0 && rr > 0.0 && pl > 0.0 && pr > 0.0 && isfinite(ul) && isfinite(ur) &&
+              isfinite(rl) && isfinite(rr) && isfinite(pl) && isfinite(pr);
     int code = 0;
     double ps = __longlong_as_double(0x7ff8000000000000ll);
     if (!ok) {
       code = GRPREC_E_NONPHYSICAL;
     } else {
-      L.c = sqrt(G.g * L.p / L.r);
-      R.c = sqrt(G.g * R.p / R.r);
+      Prim L, R;
+      prim_from(G, rl, ul, pl, L);
+      prim_from(G, rr, ur, pr, R);
       if (G.two_gm1 * (L.c + R.c) <= R.u - L.u) {
         code = GRPREC_E_VACUUM;
       } else {
         bool used;
         double p0 = start_pressure(G, L, R, guess, gate, mlp, used);
         double us, pp;
-        int it = newton_pstar(G, L, R, p0, maxit, tol, pp, us);
+        Side sl, sr;
+        int it = newton_pstar(G, L, R, p0, maxit, tol, pp, us, sl, sr);
         if (it > maxit) code = GRPREC_E_NEWTON;
         else { ps = pp; code = it; }
       }

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgrprec.so")
+LIB_PATH = os.environ.get("GRPREC_LIB", os.path.join(HERE, "libgrprec.so"))
 
 GRPREC_OK = 0
 GRPREC_E_INVALID = -1

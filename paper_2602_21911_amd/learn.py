@@ -103,6 +103,8 @@ def train(ds: Dataset, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, se
     """Adam on the mean-squared error of ln(p*/pbar); returns (params, history)."""
     import torch
     n = ds.x.shape[0]
+    if n < batch:
+        raise ValueError(f"training set has {n} problems, fewer than one batch of {batch}")
     P = init_params(ds.x, seed, device)
     grad = torch.zeros(G.GRPREC_MLP_WEIGHTS, dtype=torch.float32, device=device)
     m = torch.zeros_like(grad)
