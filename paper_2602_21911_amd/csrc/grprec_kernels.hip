@@ -477,6 +477,10 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
   }
 }
 
+#ifndef ADV_CELLS_PER_THREAD
+#define ADV_CELLS_PER_THREAD 2
+#endif
+
 template <int M>
 __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   Ctl *ctl = a.ctl;
@@ -515,7 +519,20 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     basis_mean(-0.5, -0.5 - cn, Kin);
     basis_at(-0.5 - cn, Pin);
   }
-  for (int i = gid; i < n; i += gridDim.x * blockDim.x) {
+  // Each block takes contiguous chunks of ADV_CELLS_PER_THREAD * 256 cells.
+  // Blocks are dispatched to the 8 XCDs round-robin, so block b works on
+  // chunk (b % 8) * per + b / 8: consecutive chunks run on one XCD and the
+  // cache lines they share at their ends are read once through its L2.
+  constexpr int CH = ADV_CELLS_PER_THREAD * 256;
+  const int nch = (n + CH - 1) / CH;
+  const int per = (nch + 7) / 8;
+  for (int blk = blockIdx.x; blk < 8 * per; blk += gridDim.x) {
+  const int chunk = (blk % 8) * per + blk / 8;
+  if (chunk >= nch) continue;
+#pragma unroll
+  for (int sub = 0; sub < ADV_CELLS_PER_THREAD; ++sub) {
+    const int i = chunk * CH + sub * 256 + (int)threadIdx.x;
+    if (i >= n) break;
     if (done) {
       qout[i] = qin[i];
       vout[i] = vin[i];
@@ -591,6 +608,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     }
     qout[i] = qn;
     if (!isfinite(qn)) atomicOr(&ctl->err, ERR_NONPHYS);
+  }
   }
   if (gid == 0) {
     a.seg.t[s1 * a.seg.S] = t_new;
@@ -741,7 +759,11 @@ hipError_t euler_occupancy(int block, int *blocks_per_cu) {
 
 template <int M>
 hipError_t launch_adv(const AdvArgs<M> &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((adv_step<M>), dim3(grid), dim3(256), 0, st, a);
+  (void)grid;
+  const long long ch = ADV_CELLS_PER_THREAD * 256LL;
+  const long long per = ((a.n + ch - 1) / ch + 7) / 8;
+  const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
+  hipLaunchKernelGGL((adv_step<M>), dim3(g), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
