@@ -167,15 +167,16 @@ def bench_advection(G, torch, n, order=3, steps=200, warmup=20):
         sim.close()
     per = sec / steps
     gbs = BYTES_ADV * n / per / 1e9
+    traffic = traffic_from_profiles("adv_step_order3_2e25", n) if (n == 1 << 25 and order == 3) else None
     return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per, "hbm_gbs": gbs,
-            "hbm_frac": gbs / PEAK_HBM_GBS}
+            "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm", "traffic": traffic}
 
 
 def bench_euler_single(G, torch, n, order=3, steps=50, warmup=5):
     from paper_2602_21911_amd import inputs as I
     dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
     sim = G.Simulation(G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC,
-                       schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=256)
+                       schedule=G.GRPREC_SCHED_AUTO)
     try:
         sim.run(1e9, warmup)
         sec, _ = timed_run(sim, steps, torch)

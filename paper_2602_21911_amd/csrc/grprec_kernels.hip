@@ -86,8 +86,6 @@ void euler_step(EulerArgs<M> a) {
   constexpr tab::Predictor<M> T = tab::predictor<M>();
   __shared__ double sTL[3 * NT][B];
   __shared__ double sTR[3 * NT][B];
-  __shared__ double sF[3][B];
-  __shared__ double sV[3][B];
 
   Ctl *ctl = a.ctl;
   const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
@@ -286,49 +284,46 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
-        double f[3], qs[3];
-        {
-          double QR[3];
-          if (boundary) {
-            QR[0] = q0[0]; QR[1] = q0[1]; QR[2] = q0[2];
-          } else {
-            QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+        double QR[3];
+        if (boundary) {
+          QR[0] = q0[0]; QR[1] = q0[1]; QR[2] = q0[2];
+        } else {
+          QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+        }
+        RSOut o;
+        err |= interact(G, QL, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp, a.max_newton,
+                        a.newton_tol, o);
+        pw = o.pstar;
+        st_rs += 1;
+        st_newton += o.iters;
+        st_mlp += o.mlp ? 1 : 0;
+        if (b == 0 && a.hv.ring != nullptr && useful) {
+          unsigned long long k = atomicAdd(a.hv.count, 1ull);
+          if ((long long)k < a.hv.cap) {
+            Prim L, R;
+            to_prim(G, QL[0], QL[1], QL[2], L);
+            to_prim(G, QR[0], QR[1], QR[2], R);
+            double *dst = a.hv.ring + 7 * k;
+            dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
+            dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
+            dst[6] = o.pstar;
           }
-          RSOut o;
-          err |= interact(G, QL, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp,
-                          a.max_newton, a.newton_tol, o);
-          pw = o.pstar;
-          st_rs += 1;
-          st_newton += o.iters;
-          st_mlp += o.mlp ? 1 : 0;
-          if (b == 0 && a.hv.ring != nullptr && useful) {
-            unsigned long long k = atomicAdd(a.hv.count, 1ull);
-            if ((long long)k < a.hv.cap) {
-              Prim L, R;
-              to_prim(G, QL[0], QL[1], QL[2], L);
-              to_prim(G, QR[0], QR[1], QR[2], R);
-              double *dst = a.hv.ring + 7 * k;
-              dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
-              dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
-              dst[6] = o.pstar;
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < 3; ++v) { f[v] = o.F[v]; qs[v] = o.Q[v]; }
         }
         if (b < N) {
           const double wb = pick<N>(T.w, b);
 #pragma unroll
-          for (int v = 0; v < 3; ++v) FR[v] += wb * f[v];
+          for (int v = 0; v < 3; ++v) FR[v] += wb * o.F[v];
         } else {
 #pragma unroll
-          for (int v = 0; v < 3; ++v) VR[v] = qs[v];
+          for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
         }
       }
+      // flux and datum go to the right neighbour through this slot's own
+      // right-trace column, which no other thread reads
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        sF[v][e] = FR[v];
-        sV[v][e] = VR[v];
+        sTR[v][e] = FR[v];
+        sTR[3 + v][e] = VR[v];
       }
     }
     // left end of a transmissive domain: ghost average against the left trace
@@ -366,8 +361,8 @@ void euler_step(EulerArgs<M> a) {
         if (i > 0 || a.periodic) {
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
-            FL[v] = sF[v][e - 1];
-            VL[v] = sV[v][e - 1];
+            FL[v] = sTR[v][e - 1];
+            VL[v] = sTR[3 + v][e - 1];
           }
         }
 #pragma unroll
