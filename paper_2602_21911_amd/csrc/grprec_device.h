@@ -54,6 +54,18 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(y, e, y);
 }
 
+// sqrt(x) for x > 0 finite: hardware 1/sqrt estimate and two Newton steps on
+// the pair (g ~ sqrt(x), h ~ 1/(2 sqrt(x))) (within a few ulp).
+__device__ __forceinline__ double sqrtpos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, g, x);
+  return fma(r, h, g);
+}
+
 // Conserved Q = (rho, rho u, E), ideal gas p = (g-1)(E - rho u^2 / 2).
 __device__ __forceinline__ void euler_flux(const Gas &G, double r, double m, double E, double &f0,
                                            double &f1, double &f2) {
@@ -77,7 +89,7 @@ __device__ __forceinline__ bool to_prim(const Gas &G, double r, double m, double
   w.p = G.gm1 * (E - 0.5 * m * w.u);
   bool ok = (r > 0.0) && (w.p > 0.0) && isfinite(w.u) && isfinite(w.p);
   w.ip = ok ? rcp(w.p) : 0.0;
-  w.c = ok ? sqrt(G.g * w.p * w.ir) : 0.0;
+  w.c = ok ? sqrtpos(G.g * w.p * w.ir) : 0.0;
   w.ic = ok ? rcp(w.c) : 0.0;
   return ok;
 }
@@ -89,7 +101,7 @@ __device__ __forceinline__ void prim_from(const Gas &G, double r, double u, doub
   w.p = p;
   w.ir = rcp(r);
   w.ip = rcp(p);
-  w.c = sqrt(G.g * p * w.ir);
+  w.c = sqrtpos(G.g * p * w.ir);
   w.ic = rcp(w.c);
 }
 
@@ -136,7 +148,23 @@ struct Side {
   bool rare;
 };
 
+// Weak waves: for |p/pK - 1| <= kWeak both branches of f_K and of the star
+// density agree with their second-order expansions about pK (the Hugoniot
+// curve and the isentrope have second-order contact there); the neglected
+// third-order terms, <= 2e-16 cK and 5e-17 rhoK, are below the round-off of
+// the closed forms, which lose digits to cancellation at such d.  The
+// expansions need no powers or square roots and no branch.
+constexpr double kWeak = 1e-5;
+
 __device__ __forceinline__ void side_eval(const Gas &G, double p, double ip, const Prim &K, Side &s) {
+  const double d = (p - K.p) * K.ip;
+  if (fabs(d) <= kWeak) {
+    s.rare = false;  // w is not carried on this path
+    s.w = 0.0;
+    s.f = (K.c * G.inv_g) * d * fma(-G.k2, d, 1.0);
+    s.fd = K.ir * K.ic * fma(-2.0 * G.k2, d, 1.0);
+    return;
+  }
   if (p <= K.p) {
     s.rare = true;
     s.w = pow_z(G, p * K.ip);
@@ -149,7 +177,7 @@ __device__ __forceinline__ void side_eval(const Gas &G, double p, double ip, con
     const double ak = G.two_gp1 * K.ir;
     const double bk = G.gm1_gp1 * K.p;
     const double ibp = rcp(bk + p);
-    const double sq = sqrt(ak * ibp);
+    const double sq = sqrtpos(ak * ibp);
     s.f = (p - K.p) * sq;
     s.fd = (1.0 - 0.5 * (p - K.p) * ibp) * sq;
   }
@@ -208,10 +236,12 @@ __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, cons
       if (L.u - L.c >= 0.0) {
         r = L.r; u = L.u; p = L.p;
       } else {
-        const double w = sl.rare ? sl.w : pow_z(G, ps * L.ip);
+        const double d = (ps - L.p) * L.ip;
+        const bool weak = fabs(d) <= kWeak;
+        const double w = weak ? fma(fma(G.z2, d, G.z), d, 1.0) : (sl.rare ? sl.w : pow_z(G, ps * L.ip));
         const double cs = L.c * w;
         if (us - cs < 0.0) {
-          r = L.r * dens_pow(G, w); u = us; p = ps;
+          r = L.r * (weak ? fma(fma(G.dens2, d, G.inv_g), d, 1.0) : dens_pow(G, w)); u = us; p = ps;
         } else {  // fan: u - c = 0 and u + 2c/(g-1) is carried from the left
           const double c = G.two_gp1 * (L.c + 0.5 * G.gm1 * L.u);
           const double cr = c * L.ic;
@@ -222,7 +252,7 @@ __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, cons
       }
     } else {  // left shock
       const double pm = ps * L.ip;
-      const double s = L.u - L.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
+      const double s = L.u - L.c * sqrtpos(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
       if (s >= 0.0) {
         r = L.r; u = L.u; p = L.p;
       } else {
@@ -232,7 +262,7 @@ __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, cons
   } else {
     if (ps > R.p) {  // right shock
       const double pm = ps * R.ip;
-      const double s = R.u + R.c * sqrt(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
+      const double s = R.u + R.c * sqrtpos(G.gp1_2g * pm + 0.5 * G.gm1 * G.inv_g);
       if (s <= 0.0) {
         r = R.r; u = R.u; p = R.p;
       } else {
@@ -242,10 +272,12 @@ __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, cons
       if (R.u + R.c <= 0.0) {
         r = R.r; u = R.u; p = R.p;
       } else {
-        const double w = sr.rare ? sr.w : pow_z(G, ps * R.ip);
+        const double d = (ps - R.p) * R.ip;
+        const bool weak = fabs(d) <= kWeak;
+        const double w = weak ? fma(fma(G.z2, d, G.z), d, 1.0) : (sr.rare ? sr.w : pow_z(G, ps * R.ip));
         const double cs = R.c * w;
         if (us + cs >= 0.0) {
-          r = R.r * dens_pow(G, w); u = us; p = ps;
+          r = R.r * (weak ? fma(fma(G.dens2, d, G.inv_g), d, 1.0) : dens_pow(G, w)); u = us; p = ps;
         } else {  // fan: u + c = 0 and u - 2c/(g-1) is carried from the right
           const double c = G.two_gp1 * (R.c - 0.5 * G.gm1 * R.u);
           const double cr = c * R.ic;
@@ -332,25 +364,34 @@ __device__ __forceinline__ double start_pressure(const Gas &G, const Prim &L, co
   return pv;
 }
 
+// Start value for the first Riemann problem of an interface from conserved
+// states: the learned proposal where the data jump exceeds the gate, else 0
+// (meaning PVRS).  Non-physical data give 0 and are reported by interact().
+__device__ __noinline__ double learned_start(const Gas &G, const double QL[3], const double QR[3],
+                                             double gate, const float *mlp, bool &used) {
+  Prim L, R;
+  used = false;
+  if (!(to_prim(G, QL[0], QL[1], QL[2], L) && to_prim(G, QR[0], QR[1], QR[2], R))) return 0.0;
+  const double p = start_pressure(G, L, R, 1, gate, mlp, used);
+  return used ? p : 0.0;
+}
+
 // Full interface interaction: exact Riemann solution at x/t = 0 between two
 // conserved states; returns error bits, the physical flux there and the state.
-// pguess > 0 overrides the start value (warm start).
+// Newton starts from pguess when it is positive, else from PVRS.
 struct RSOut {
   double F[3];
   double Q[3];
   double pstar;
   int iters;
-  bool mlp;
 };
 
 __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], const double QR[3],
-                                             double pguess, int guess, double gate, const float *mlp,
-                                             int maxit, double tol, RSOut &o) {
+                                             double pguess, int maxit, double tol, RSOut &o) {
   Prim L, R;
   bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
   bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
   o.iters = 0;
-  o.mlp = false;
   if (!(okl && okr)) {
     o.F[0] = o.F[1] = o.F[2] = 0.0;
     o.Q[0] = QL[0]; o.Q[1] = QL[1]; o.Q[2] = QL[2];
@@ -363,7 +404,7 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
     o.pstar = 0.0;
     return ERR_VACUUM;
   }
-  double p0 = pguess > 0.0 ? pguess : start_pressure(G, L, R, guess, gate, mlp, o.mlp);
+  double p0 = pguess > 0.0 ? pguess : pvrs(L, R);
   double ps, us;
   Side sl, sr;
   int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us, sl, sr);

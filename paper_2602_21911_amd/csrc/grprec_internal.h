@@ -39,6 +39,10 @@ struct Gas {
   int dens_k;      // 2/(g-1) when it is an integer (5 for g = 1.4), else 0
   double inv_n, nm1_n;  // 1/root_n, (root_n - 1)/root_n
   float inv_nf;
+  // second-order coefficients of the weak-wave expansions about p = pK
+  double k2;       // f_K  = (cK/g) d (1 - k2 d),        k2 = (g+1)/(4g)
+  double z2;       // w    = 1 + z d + z2 d^2,          z2 = z (z-1)/2
+  double dens2;    // rho* = rhoK (1 + d/g + dens2 d^2), dens2 = -(g-1)/(2g^2)
 };
 
 namespace gasc {
@@ -66,6 +70,9 @@ constexpr Gas make_gas(double g) {
   G.inv_n = G.root_n ? 1.0 / G.root_n : 0.0;
   G.nm1_n = G.root_n ? (G.root_n - 1.0) / G.root_n : 0.0;
   G.inv_nf = (float)G.inv_n;
+  G.k2 = (g + 1.0) / (4.0 * g);
+  G.z2 = 0.5 * G.z * (G.z - 1.0);
+  G.dens2 = -(g - 1.0) / (2.0 * g * g);
   return G;
 }
 

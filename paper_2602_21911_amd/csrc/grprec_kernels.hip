@@ -109,7 +109,7 @@ void euler_step(EulerArgs<M> a) {
   const int e = threadIdx.x;
   const int tc = a.tc, ti = a.ti;
   unsigned err = 0;
-  unsigned long long st_rs = 0, st_newton = 0, st_sweeps = 0, st_cells = 0, st_mlp = 0;
+  unsigned st_rs = 0, st_newton = 0, st_sweeps = 0, st_cells = 0, st_mlp = 0;
 
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int4 td = a.tiles[tile];
@@ -290,13 +290,21 @@ void euler_step(EulerArgs<M> a) {
         } else {
           QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
         }
+        double p0 = 0.0;  // PVRS
+        if (b == 0) {
+          if (a.guess == 1) {
+            bool used;
+            p0 = learned_start(G, QL, QR, a.gate, a.mlp, used);
+            st_mlp += used ? 1 : 0;
+          }
+        } else if (a.warm || a.guess == 1) {
+          p0 = pw;  // later times start from the previous time's star pressure
+        }
         RSOut o;
-        err |= interact(G, QL, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp, a.max_newton,
-                        a.newton_tol, o);
+        err |= interact(G, QL, QR, p0, a.max_newton, a.newton_tol, o);
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
-        st_mlp += o.mlp ? 1 : 0;
         if (b == 0 && a.hv.ring != nullptr && useful) {
           unsigned long long k = atomicAdd(a.hv.count, 1ull);
           if ((long long)k < a.hv.cap) {
@@ -333,13 +341,21 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
+        double p0 = 0.0;
+        if (b == 0) {
+          if (a.guess == 1) {
+            bool used;
+            p0 = learned_start(G, q0, QR, a.gate, a.mlp, used);
+            st_mlp += used ? 1 : 0;
+          }
+        } else if (a.warm || a.guess == 1) {
+          p0 = pw;
+        }
         RSOut o;
-        err |= interact(G, q0, QR, (a.warm && b > 0) ? pw : 0.0, a.guess, a.gate, a.mlp, a.max_newton,
-                        a.newton_tol, o);
+        err |= interact(G, q0, QR, p0, a.max_newton, a.newton_tol, o);
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
-        st_mlp += o.mlp ? 1 : 0;
         if (b < N) {
           const double wb = pick<N>(T.w, b);
 #pragma unroll
@@ -402,17 +418,15 @@ void euler_step(EulerArgs<M> a) {
   }
   if (err) atomicOr(&ctl->err, err);
   if (stats) {
-    st_rs = wave_sum_u64(st_rs);
-    st_newton = wave_sum_u64(st_newton);
-    st_sweeps = wave_sum_u64(st_sweeps);
-    st_cells = wave_sum_u64(st_cells);
-    st_mlp = wave_sum_u64(st_mlp);
+    const unsigned long long r0 = wave_sum_u64(st_rs), r1 = wave_sum_u64(st_newton),
+                             r2 = wave_sum_u64(st_sweeps), r3 = wave_sum_u64(st_cells),
+                             r4 = wave_sum_u64(st_mlp);
     if ((threadIdx.x & 63) == 0) {
-      atomicAdd(&ctl->stat[0], st_rs);
-      atomicAdd(&ctl->stat[1], st_newton);
-      atomicAdd(&ctl->stat[2], st_sweeps);
-      atomicAdd(&ctl->stat[3], st_cells);
-      atomicAdd(&ctl->stat[4], st_mlp);
+      atomicAdd(&ctl->stat[0], r0);
+      atomicAdd(&ctl->stat[1], r1);
+      atomicAdd(&ctl->stat[2], r2);
+      atomicAdd(&ctl->stat[3], r3);
+      atomicAdd(&ctl->stat[4], r4);
     }
   }
 }
@@ -623,7 +637,7 @@ __global__ void init_interfaces_euler(double *v0, const double *v1, int ti, Gas 
     double QL[3] = {v0[k], v0[ti + k], v0[2 * ti + k]};
     double QR[3] = {v1[k], v1[ti + k], v1[2 * ti + k]};
     RSOut o;
-    err |= interact(G, QL, QR, 0.0, 0, 0.0, nullptr, maxit, tol, o);
+    err |= interact(G, QL, QR, 0.0, maxit, tol, o);
     v0[k] = o.Q[0];
     v0[ti + k] = o.Q[1];
     v0[2 * ti + k] = o.Q[2];

@@ -202,3 +202,39 @@ def test_riemann_batch_matches_oracle(G):
         else:
             assert int(it[k]) == rc, (k, it[k], rc)
     assert n_ok > 1000
+
+
+def test_riemann_batch_weak_waves(G):
+    """Near-equal states (|p*/pK - 1| from 1e-12 to 1e-3) straddle the weak-wave
+    threshold of the solver; p* agrees with the oracle's closed forms."""
+    rng = np.random.default_rng(12)
+    n = 3000
+    base = np.stack([rng.uniform(0.3, 3, n), rng.uniform(-1, 1, n), rng.uniform(0.3, 3, n)], 1)
+    eps = 10.0 ** rng.uniform(-12, -3, n)
+    WL = base * (1 + eps[:, None] * rng.normal(size=(n, 3)))
+    WR = base * (1 + eps[:, None] * rng.normal(size=(n, 3)))
+    ps, it = G.grprec_riemann_batch(torch.from_numpy(WL).cuda(), torch.from_numpy(WR).cuda())
+    ps = ps.cpu().numpy()
+    for k in range(n):
+        p_ref, _, _, _ = oracle.riemann(1.4, WL[k], WR[k])
+        assert abs(ps[k] - p_ref) <= 1e-13 * p_ref, (k, eps[k])
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_euler_weak_jumps_parity(G, order):
+    """Smooth data with a tiny superposed perturbation: every interface problem
+    is a weak wave; both sampling branches and the threshold are crossed."""
+    n = 200
+    dx, q, vl, vr = acoustic_case(n, amp=1e-4)
+    c = oracle_cfg(oracle.EULER, order, oracle.PERIODIC)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_PERIODIC,
+                   schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=64)
+    try:
+        sim.run(0.2)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 0.2)
+        qg, vg, t, steps = sim.numpy_state()
+        assert steps == kr
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
