@@ -34,7 +34,14 @@ __device__ __forceinline__ void wave_segmented_max(int seg, double val, unsigned
     if (lane + d < 64 && os == seg) val = nanmax(val, ov);
   }
   int prev = __shfl_up(seg, 1, 64);
-  if (seg >= 0 && (lane == 0 || prev != seg)) atomicMax(base + seg, dbits(val));
+  if (seg >= 0 && (lane == 0 || prev != seg)) {
+    // the target only grows while it accumulates, so a run whose maximum does
+    // not exceed the value already there has nothing to add; skipping it keeps
+    // a long domain's many waves from queueing on one address
+    const unsigned long long bits = dbits(val);
+    if (__hip_atomic_load(base + seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits)
+      atomicMax(base + seg, bits);
+  }
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -337,43 +344,40 @@ __device__ __forceinline__ float mlp_eval(const float *__restrict__ P, const flo
   return y;
 }
 
+// True when the data jump is large: |dp|/pbar + |drho|/rhobar + |du|/cbar
+// above the gate (evaluated without divisions); a negative gate always passes.
+__device__ __forceinline__ bool jump_exceeds(const Prim &L, const Prim &R, double gate) {
+  const double pbar = 0.5 * (L.p + R.p), rbar = 0.5 * (L.r + R.r), cbar = 0.5 * (L.c + R.c);
+  const double lhs = fabs(R.p - L.p) * rbar * cbar + fabs(R.r - L.r) * pbar * cbar +
+                     fabs(R.u - L.u) * pbar * rbar;
+  return gate < 0.0 || lhs > gate * pbar * rbar * cbar;
+}
+
+// The network's star-pressure proposal, or 0 when it is not positive and
+// finite.  Kept out of line: it is large and, behind the gate, rarely taken.
+__device__ __noinline__ double learned_pressure(const Gas &G, const Prim &L, const Prim &R,
+                                                const float *mlp) {
+  float x[6];
+  double pb;
+  mlp_features(G, L, R, x, pb);
+  const float y = mlp_eval(mlp, x);
+  const double p0 = pb * exp((double)y);
+  return (p0 > 0.0 && isfinite(p0)) ? p0 : 0.0;
+}
+
 // Starting pressure: learned proposal when asked for and the data jump is
-// large (relative jump above the gate), else PVRS.  A non-finite or
-// non-positive proposal falls back to PVRS.
+// large, else PVRS.  A non-finite or non-positive proposal falls back to PVRS.
 __device__ __forceinline__ double start_pressure(const Gas &G, const Prim &L, const Prim &R, int guess,
                                                  double gate, const float *mlp, bool &used_mlp) {
   used_mlp = false;
-  double pv = pvrs(L, R);
-  if (guess == 1 && mlp != nullptr) {
-    // relative jump |dp|/pbar + |drho|/rhobar + |du|/cbar > gate, without divisions
-    const double pbar = 0.5 * (L.p + R.p), rbar = 0.5 * (L.r + R.r), cbar = 0.5 * (L.c + R.c);
-    const double lhs = fabs(R.p - L.p) * rbar * cbar + fabs(R.r - L.r) * pbar * cbar +
-                       fabs(R.u - L.u) * pbar * rbar;
-    if (gate < 0.0 || lhs > gate * pbar * rbar * cbar) {
-      float x[6];
-      double pb;
-      mlp_features(G, L, R, x, pb);
-      float y = mlp_eval(mlp, x);
-      double p0 = pb * exp((double)y);
-      if (p0 > 0.0 && isfinite(p0)) {
-        used_mlp = true;
-        return p0;
-      }
+  if (guess == 1 && mlp != nullptr && jump_exceeds(L, R, gate)) {
+    const double p0 = learned_pressure(G, L, R, mlp);
+    if (p0 > 0.0) {
+      used_mlp = true;
+      return p0;
     }
   }
-  return pv;
-}
-
-// Start value for the first Riemann problem of an interface from conserved
-// states: the learned proposal where the data jump exceeds the gate, else 0
-// (meaning PVRS).  Non-physical data give 0 and are reported by interact().
-__device__ __noinline__ double learned_start(const Gas &G, const double QL[3], const double QR[3],
-                                             double gate, const float *mlp, bool &used) {
-  Prim L, R;
-  used = false;
-  if (!(to_prim(G, QL[0], QL[1], QL[2], L) && to_prim(G, QR[0], QR[1], QR[2], R))) return 0.0;
-  const double p = start_pressure(G, L, R, 1, gate, mlp, used);
-  return used ? p : 0.0;
+  return pvrs(L, R);
 }
 
 // Full interface interaction: exact Riemann solution at x/t = 0 between two
@@ -386,8 +390,12 @@ struct RSOut {
   int iters;
 };
 
+// With mlp != nullptr and no positive pguess, the start is start_pressure()'s
+// (learned where the jump passes the gate); `used` reports that choice.
 __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], const double QR[3],
-                                             double pguess, int maxit, double tol, RSOut &o) {
+                                             double pguess, int maxit, double tol, RSOut &o,
+                                             const float *mlp = nullptr, double gate = 0.0,
+                                             bool *used = nullptr) {
   Prim L, R;
   bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
   bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
@@ -404,7 +412,16 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
     o.pstar = 0.0;
     return ERR_VACUUM;
   }
-  double p0 = pguess > 0.0 ? pguess : pvrs(L, R);
+  double p0;
+  if (pguess > 0.0) {
+    p0 = pguess;
+  } else if (mlp != nullptr) {
+    bool u;
+    p0 = start_pressure(G, L, R, 1, gate, mlp, u);
+    *used = u;
+  } else {
+    p0 = pvrs(L, R);
+  }
   double ps, us;
   Side sl, sr;
   int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us, sl, sr);

@@ -290,18 +290,14 @@ void euler_step(EulerArgs<M> a) {
         } else {
           QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
         }
-        double p0 = 0.0;  // PVRS
-        if (b == 0) {
-          if (a.guess == 1) {
-            bool used;
-            p0 = learned_start(G, QL, QR, a.gate, a.mlp, used);
-            st_mlp += used ? 1 : 0;
-          }
-        } else if (a.warm || a.guess == 1) {
-          p0 = pw;  // later times start from the previous time's star pressure
-        }
+        // first time: PVRS or the learned start; later times start from the
+        // previous time's star pressure when warm starts are on
+        const bool warm = b > 0 && (a.warm || a.guess == 1);
+        const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
+        bool used = false;
         RSOut o;
-        err |= interact(G, QL, QR, p0, a.max_newton, a.newton_tol, o);
+        err |= interact(G, QL, QR, warm ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp, a.gate, &used);
+        st_mlp += used ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
@@ -341,18 +337,12 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
-        double p0 = 0.0;
-        if (b == 0) {
-          if (a.guess == 1) {
-            bool used;
-            p0 = learned_start(G, q0, QR, a.gate, a.mlp, used);
-            st_mlp += used ? 1 : 0;
-          }
-        } else if (a.warm || a.guess == 1) {
-          p0 = pw;
-        }
+        const bool warm = b > 0 && (a.warm || a.guess == 1);
+        const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
+        bool used = false;
         RSOut o;
-        err |= interact(G, q0, QR, p0, a.max_newton, a.newton_tol, o);
+        err |= interact(G, q0, QR, warm ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp, a.gate, &used);
+        st_mlp += used ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
