@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "libgrprec_oracle.so")
 OK, E_INVALID, E_NONPHYSICAL, E_VACUUM, E_NEWTON, E_PREDICTOR = 0, -1, -4, -5, -6, -7
 ADVECTION, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
+LINEAR, NONLINEAR = 0, 1          # GRPrec (Sec. 3.1) or GRPrecNL (Sec. 3.3-3.4)
 
 
 def build(force: bool = True) -> str:
@@ -38,7 +39,9 @@ class Cfg(ctypes.Structure):
                 ("lam", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("bc_left", ctypes.c_int), ("bc_right", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int),
-                ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int)]
+                ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
+                ("recon", ctypes.c_int), ("nl_lambda_c", ctypes.c_double),
+                ("nl_eps", ctypes.c_double), ("nl_r", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -76,6 +79,11 @@ def lib():
         L.orc_run_segment.argtypes = [ctypes.POINTER(Cfg), ctypes.c_int, ctypes.c_double, _D, _D,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _I64,
                                       ctypes.POINTER(Stats)]
+        L.orc_side_matrix.argtypes = [ctypes.c_int, ctypes.c_int, _D]
+        L.orc_oi.argtypes = [ctypes.c_int, _D, ctypes.c_double]
+        L.orc_oi.restype = ctypes.c_double
+        L.orc_eigvec.argtypes = [ctypes.c_double, _D, _D]
+        L.orc_recon_nl_cell.argtypes = [ctypes.POINTER(Cfg), ctypes.c_double, _D, _D, _D]
         L.orc_run_segments.argtypes = [ctypes.POINTER(Cfg), ctypes.c_int, _I64, _D, _D, _D, _D,
                                        ctypes.c_double, ctypes.c_int64, ctypes.POINTER(Stats)]
         _lib = L
@@ -88,9 +96,14 @@ def _p(a: np.ndarray):
 
 
 def cfg(system=ADVECTION, order=3, cfl=0.9, lam=1.0, gamma=1.4, bc=PERIODIC, newton_tol=1e-12,
-        newton_max=50, picard_tol=1e-13, picard_max=64) -> Cfg:
+        newton_max=50, picard_tol=1e-13, picard_max=64, recon=LINEAR, nl_lambda_c=10.0,
+        nl_eps=1e-14, nl_r=4.0) -> Cfg:
+    """GRPrecNL weights: r and eps as printed (Sec. 3.3).  lambda_C defaults to
+    10, the value under which the scheme reproduces the paper's GRPrecNL
+    results (Sec. 4.2.3 table, Sec. 4.2.2 square wave); the printed 1e9 makes
+    GRPrecNL coincide with GRPrec on smooth data (pass nl_lambda_c=1e9)."""
     return Cfg(system, order - 1, cfl, lam, gamma, bc, bc, newton_tol, newton_max, picard_tol,
-               picard_max)
+               picard_max, recon, nl_lambda_c, nl_eps, nl_r)
 
 
 class OracleError(RuntimeError):
@@ -118,6 +131,41 @@ def recon_matrix(m: int) -> np.ndarray:
     R = np.zeros((m + 1, 5))
     _chk(lib().orc_recon_matrix(m, _p(R)), "recon_matrix")
     return R
+
+
+def side_matrix(m: int, side: int) -> np.ndarray:
+    """(m+1) x 7 matrix of GRPrecNL's left (side 0) or right (side 1)
+    polynomial: monomial coefficients from (q_{i-1}, q_i, q_{i+1}, V_{i-1/2},
+    V_{i+1/2}, V_{i-3/2}, V_{i+3/2})."""
+    M = np.zeros((m + 1, 7))
+    _chk(lib().orc_side_matrix(m, side, _p(M)), "side_matrix")
+    return M
+
+
+def oi(coef: np.ndarray, dx: float) -> float:
+    """Oscillation indicator of a polynomial given by monomial coefficients in
+    xi = (x - x_i)/dx."""
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    return lib().orc_oi(len(c) - 1, _p(c), dx)
+
+
+def eigvec(gamma: float, Q) -> np.ndarray:
+    """Right eigenvectors (columns) of the Euler flux Jacobian at conserved Q."""
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    R = np.zeros((3, 3))
+    _chk(lib().orc_eigvec(gamma, _p(q), _p(R)), "eigvec")
+    return R
+
+
+def recon_nl_cell(c: Cfg, dx: float, d: np.ndarray):
+    """GRPrecNL polynomial of one cell: d is [nv][7] data, returns
+    (coefficients [nv][m+1], weights [nv][3])."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    nv = d.shape[0]
+    coef = np.zeros((nv, c.m + 1))
+    beta = np.zeros((nv, 3))
+    _chk(lib().orc_recon_nl_cell(ctypes.byref(c), dx, _p(d), _p(coef), _p(beta)), "recon_nl_cell")
+    return coef, beta
 
 
 def predictor_matrices(m: int):

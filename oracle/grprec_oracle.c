@@ -12,6 +12,10 @@
  *   - reconstruction: the defining conditions of Sec. 3.1 (eqs. interpleft,
  *     interpright, conservation and the two least-squares functionals) are
  *     assembled as a KKT system and solved by Gaussian elimination;
+ *   - GRPrecNL (Sec. 3.3-3.4): left and right polynomials from their square
+ *     condition systems, oscillation indicators by Gauss quadrature of the
+ *     squared derivatives, weights of eq. omega; for the Euler equations in
+ *     characteristic variables (Sec. 3.1);
  *   - the GRP_m solver is DET (Sec. 2 and Sec. 4.1): a local space-time DG
  *     predictor iterated to a fixed point, then classical Riemann problems at
  *     the time integration points of the flux integral (eq. numfluxes);
@@ -49,6 +53,10 @@ typedef struct {
   int newton_max;
   double picard_tol; /* predictor stop: max|change| <= tol*(1+max|q|) */
   int picard_max;
+  int recon;        /* 0 = GRPrec (Sec. 3.1), 1 = GRPrecNL (Sec. 3.3-3.4) */
+  double nl_lambda_c; /* GRPrecNL linear weight of the centred polynomial (1e9) */
+  double nl_eps;      /* GRPrecNL epsilon (1e-14) */
+  double nl_r;        /* GRPrecNL exponent r (4) */
 } orc_cfg;
 
 typedef struct {
@@ -185,7 +193,9 @@ static double orc_lagr_d(int n, const double *g, int k, double x) {
 
 static void orc_cond_row(int m, int which, double *row) {
   /* which: 0 = mean cell i-1, 1 = mean cell i, 2 = mean cell i+1,
-   *        3 = value at -1/2, 4 = value at +1/2 */
+   *        3 = value at -1/2, 4 = value at +1/2,
+   *        5 = value at -3/2, 6 = value at +3/2 (GRPrecNL, degree 4 only) */
+  static const double point[7] = {0.0, 0.0, 0.0, -0.5, 0.5, -1.5, 1.5};
   for (int j = 0; j <= m; ++j) {
     double a, b;
     switch (which) {
@@ -197,7 +207,7 @@ static void orc_cond_row(int m, int which, double *row) {
     if (which <= 2)
       row[j] = (pow(b, j + 1) - pow(a, j + 1)) / (j + 1.0); /* interval length 1 */
     else
-      row[j] = pow(which == 3 ? -0.5 : 0.5, j);
+      row[j] = pow(point[which], j);
   }
 }
 
@@ -252,6 +262,100 @@ static double orc_poly(int m, const double *c, double xi) {
 }
 
 /* ------------------------------------------------------------------ */
+/* GRPrecNL, Sec. 3.3-3.4: the polynomial of cell i is a convex combination of
+ * a left, the centred (GRPrec) and a right polynomial of degree m, weighted by
+ * oscillation indicators.  Data d = (q_{i-1}, q_i, q_{i+1}, V_{i-1/2},
+ * V_{i+1/2}, V_{i-3/2}, V_{i+3/2}), indexed as in orc_cond_row.  The left and
+ * right polynomials satisfy all their conditions exactly (square systems):
+ *   degree 1: L = mean of i and the value at -1/2;
+ *             R = mean of i and the value at +1/2;
+ *   degree 2: L = means of i-1, i and the value at +1/2;
+ *             R = means of i, i+1 and the value at -1/2;
+ *   degree 3: L = means of i-1, i, i+1 and the value at -1/2;
+ *             R = means of i-1, i, i+1 and the value at +1/2;
+ *   degree 4: L = means of i-1, i, i+1 and the values at -1/2 and -3/2;
+ *             R = means of i-1, i, i+1 and the values at +1/2 and +3/2
+ *             (the paper's paragraph calls this polynomial "fifth degree"; it
+ *             has five coefficients, so degree 4).
+ * Weights: omega_k = lambda_k / (eps + OI_k)^r, beta_k = omega_k / sum omega,
+ * lambda_L = lambda_R = 1; r, eps and lambda_C come from the configuration.
+ * The paper prints r = 4, eps = 1e-14, lambda_C = 1e9 (eq. omega).  With
+ * lambda_C = 1e9 the centred polynomial wins wherever the three indicators are
+ * within a factor 1e9^(1/4) ~ 178 of each other, which on smooth data makes
+ * GRPrecNL coincide with GRPrec; the paper's GRPrecNL table (Sec. 4.2.3) and
+ * its square-wave remarks (Sec. 4.2.2) are reproduced with lambda_C ~ 10. */
+#define ORC_NL_LAMBDA_SIDE 1.0
+
+int orc_side_matrix(int m, int side /* 0 = left, 1 = right */, double *M /* (m+1) x 7 */) {
+  static const int cond[4][2][5] = {{{1, 3}, {1, 4}},
+                                    {{0, 1, 4}, {1, 2, 3}},
+                                    {{0, 1, 2, 3}, {0, 1, 2, 4}},
+                                    {{0, 1, 2, 3, 5}, {0, 1, 2, 4, 6}}};
+  if (m < 1 || m > 4 || side < 0 || side > 1) return ORC_E_INVALID;
+  int nc = m + 1;
+  double A[MAXN * MAXN], rhs[MAXN * 7], row[MAXN];
+  memset(rhs, 0, sizeof(rhs));
+  for (int r = 0; r < nc; ++r) {
+    orc_cond_row(m, cond[m - 1][side][r], row);
+    for (int j = 0; j < nc; ++j) A[r * nc + j] = row[j];
+    rhs[r * 7 + cond[m - 1][side][r]] = 1.0;
+  }
+  if (orc_gauss_solve(nc, A, 7, rhs) != 0) return ORC_E_INVALID;
+  memcpy(M, rhs, sizeof(double) * nc * 7);
+  return ORC_OK;
+}
+
+/* Oscillation indicator of Sec. 3.3 for p(x) = sum_j c_j ((x - x_i)/dx)^j on
+ * cell i:  OI = sum_{l=1..m} integral over the cell of (d^l p/dx^l)^2 dx^(2l) dx,
+ * the dx^(2l) factor as printed.  The integral is 5-point Gauss-Legendre,
+ * exact here (the integrand has degree at most 6). */
+double orc_oi(int m, const double *c, double dx) {
+  double g[5], w[5];
+  orc_gauss_legendre(5, g, w);
+  double oi = 0.0;
+  for (int l = 1; l <= m; ++l) {
+    for (int k = 0; k < 5; ++k) {
+      double xi = g[k] - 0.5; /* x = x_i + xi dx */
+      double d = 0.0;         /* d^l p / dx^l at x */
+      for (int j = l; j <= m; ++j) {
+        double f = 1.0;
+        for (int t = 0; t < l; ++t) f *= (double)(j - t);
+        d += c[j] * f * pow(xi, j - l) / pow(dx, l);
+      }
+      oi += dx * w[k] * d * d * pow(dx, 2 * l);
+    }
+  }
+  return oi;
+}
+
+/* One scalar component: coefficients of beta_L p_L + beta_C p_C + beta_R p_R
+ * and the three weights. */
+static void orc_nl_scalar(const orc_cfg *cf, double dx, const double *RC, const double *ML,
+                          const double *MR, const double *d, double *c, double *beta) {
+  int m = cf->m;
+  double cl[MAXN], cc[MAXN], cr[MAXN];
+  for (int r = 0; r <= m; ++r) {
+    cl[r] = cc[r] = cr[r] = 0.0;
+    for (int k = 0; k < 7; ++k) {
+      cl[r] += ML[r * 7 + k] * d[k];
+      cr[r] += MR[r * 7 + k] * d[k];
+    }
+    for (int k = 0; k < 5; ++k) cc[r] += RC[r * 5 + k] * d[k];
+  }
+  double wl = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi(m, cl, dx), cf->nl_r);
+  double wc = cf->nl_lambda_c / pow(cf->nl_eps + orc_oi(m, cc, dx), cf->nl_r);
+  double wr = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi(m, cr, dx), cf->nl_r);
+  double ws = wl + wc + wr;
+  double bl = wl / ws, bc = wc / ws, br = wr / ws;
+  for (int r = 0; r <= m; ++r) c[r] = bl * cl[r] + bc * cc[r] + br * cr[r];
+  if (beta) {
+    beta[0] = bl;
+    beta[1] = bc;
+    beta[2] = br;
+  }
+}
+
+/* ------------------------------------------------------------------ */
 /* Physics (Sec. 4.2 and Sec. 4.3, eqs. Euler-gen, Euler-variables, ideal gas). */
 
 static int orc_nvar(const orc_cfg *c) { return c->system == 0 ? 1 : 3; }
@@ -279,6 +383,61 @@ static void orc_prim_to_cons(double g, const double *W, double *Q) {
   Q[0] = W[0];
   Q[1] = W[0] * W[1];
   Q[2] = W[2] / (g - 1.0) + 0.5 * W[0] * W[1] * W[1];
+}
+
+/* Right eigenvectors of the Euler flux Jacobian at Q, as the columns of Rm
+ * (row-major), for the eigenvalues u - c, u, u + c:
+ *   (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c),
+ * H = (E + p)/rho the specific total enthalpy. */
+int orc_eigvec(double g, const double *Q, double *Rm) {
+  double W[3];
+  orc_cons_to_prim(g, Q, W);
+  if (!(W[0] > 0.0) || !(W[2] > 0.0) || !isfinite(W[1])) return ORC_E_NONPHYSICAL;
+  double u = W[1], c = sqrt(g * W[2] / W[0]), H = (Q[2] + W[2]) / W[0];
+  double col[3][3] = {{1.0, u - c, H - u * c}, {1.0, u, 0.5 * u * u}, {1.0, u + c, H + u * c}};
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) Rm[r * 3 + k] = col[k][r];
+  return ORC_OK;
+}
+
+/* GRPrecNL polynomial of one cell.  d holds the seven data of every conserved
+ * variable ([nv][7]); coef receives [nv][m+1] monomial coefficients in
+ * xi = (x - x_i)/dx; beta (optional) the weights [nv][3].  For the Euler
+ * equations the data are first written in characteristic variables with the
+ * eigenvectors at the cell average q_i (the paper reconstructs systems in
+ * characteristic variables, Sec. 3.1), each characteristic field is
+ * reconstructed as a scalar, and the result is projected back; beta then
+ * refers to the characteristic fields. */
+int orc_recon_nl_cell(const orc_cfg *cf, double dx, const double *d, double *coef, double *beta) {
+  int m = cf->m;
+  double RC[MAXN * 5], ML[MAXN * 7], MR[MAXN * 7];
+  if (orc_recon_matrix(m, RC) || orc_side_matrix(m, 0, ML) || orc_side_matrix(m, 1, MR))
+    return ORC_E_INVALID;
+  if (cf->system == 0) {
+    orc_nl_scalar(cf, dx, RC, ML, MR, d, coef, beta);
+    return ORC_OK;
+  }
+  double Qbar[3] = {d[0 * 7 + 1], d[1 * 7 + 1], d[2 * 7 + 1]};
+  double Rm[9], Lm[9], Rw[9];
+  int rc = orc_eigvec(cf->gamma, Qbar, Rm);
+  if (rc != ORC_OK) return rc;
+  memcpy(Rw, Rm, sizeof(Rw));
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) Lm[r * 3 + k] = (r == k) ? 1.0 : 0.0;
+  if (orc_gauss_solve(3, Rw, 3, Lm) != 0) return ORC_E_NONPHYSICAL; /* Lm = Rm^-1 */
+  double w[3][7], cw[3][MAXN];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 7; ++j) {
+      w[k][j] = 0.0;
+      for (int v = 0; v < 3; ++v) w[k][j] += Lm[k * 3 + v] * d[v * 7 + j];
+    }
+  for (int k = 0; k < 3; ++k) orc_nl_scalar(cf, dx, RC, ML, MR, w[k], cw[k], beta ? beta + 3 * k : NULL);
+  for (int v = 0; v < 3; ++v)
+    for (int r = 0; r <= m; ++r) {
+      coef[v * (m + 1) + r] = 0.0;
+      for (int k = 0; k < 3; ++k) coef[v * (m + 1) + r] += Rm[v * 3 + k] * cw[k][r];
+    }
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -637,7 +796,7 @@ static int orc_check_state(const orc_cfg *cf, const double *Q) {
 int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const double *v, double t,
                      double t_end, double *q_out, double *v_out, double *dt_out, double *t_out,
                      orc_stats *st) {
-  if (n < 1 || cf->m < 1 || cf->m > 4) return ORC_E_INVALID;
+  if (n < 1 || cf->m < 1 || cf->m > 4 || cf->recon < 0 || cf->recon > 1) return ORC_E_INVALID;
   int m = cf->m, nv = orc_nvar(cf), nn = m + 1;
   int per = (cf->bc_left == 0);
   double R[5 * 5];
@@ -667,17 +826,36 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
       if (ip > n - 1) ip = n - 1;
     }
     double w[3 * MAXN], qh[3 * MAXN * MAXN];
+    /* the seven data of each variable; V_{i-3/2} and V_{i+3/2} are read by
+     * GRPrecNL at degree 4 only.  Beyond a transmissive end they belong to the
+     * ghost cell, a constant state equal to the end average. */
+    double d[3 * 7], coef[3 * MAXN];
     for (int vv = 0; vv < nv; ++vv) {
-      double d[5] = {q[vv * n + im], q[vv * n + i], q[vv * n + ip], v[vv * (n + 1) + i],
-                     v[vv * (n + 1) + i + 1]};
-      double c[MAXN];
-      for (int r = 0; r <= m; ++r) {
-        double acc = 0.0;
-        for (int k = 0; k < 5; ++k) acc += R[r * 5 + k] * d[k];
-        c[r] = acc;
+      const double *qv = q + vv * n, *vvv = v + vv * (n + 1);
+      double vm, vp;
+      if (per) {
+        vm = vvv[(i - 1 + n) % n];
+        vp = vvv[(i + 2) % n];
+      } else {
+        vm = (i >= 1) ? vvv[i - 1] : qv[0];
+        vp = (i + 2 <= n) ? vvv[i + 2] : qv[n - 1];
       }
-      for (int a = 0; a < nn; ++a) w[vv * nn + a] = orc_poly(m, c, s.g[a] - 0.5);
+      double dd[7] = {qv[im], qv[i], qv[ip], vvv[i], vvv[i + 1], vm, vp};
+      memcpy(d + vv * 7, dd, sizeof(dd));
     }
+    if (cf->recon == 1) {
+      rc = orc_recon_nl_cell(cf, dx, d, coef, NULL);
+      if (rc != ORC_OK) break;
+    } else {
+      for (int vv = 0; vv < nv; ++vv)
+        for (int r = 0; r <= m; ++r) {
+          double acc = 0.0;
+          for (int k = 0; k < 5; ++k) acc += R[r * 5 + k] * d[vv * 7 + k];
+          coef[vv * (m + 1) + r] = acc;
+        }
+    }
+    for (int vv = 0; vv < nv; ++vv)
+      for (int a = 0; a < nn; ++a) w[vv * nn + a] = orc_poly(m, coef + vv * (m + 1), s.g[a] - 0.5);
     int it = 0;
     rc = orc_predict(cf, &s, nu, w, qh, &it);
     if (st) {
