@@ -62,6 +62,14 @@ enum {
   GRPREC_GUESS_PVRS = 0, /* linearised Riemann solver, floored at 1e-6 min(pL,pR) */
   GRPREC_GUESS_MLP = 1   /* learned proposal where the data jump is large, else PVRS */
 };
+/* Reconstruction operator. */
+enum {
+  GRPREC_RECON_LINEAR = 0, /* GRPrec, Sec. 3.1 */
+  GRPREC_RECON_NL = 1      /* GRPrecNL, Sec. 3.3-3.4: convex combination of a left, the
+                              centred (GRPrec) and a right polynomial with weights
+                              omega_k = lambda_k / (eps + OI_k)^4, lambda_L = lambda_R = 1;
+                              for the Euler equations in characteristic variables */
+};
 /* How cells are grouped into workgroup tiles (Euler). */
 enum {
   GRPREC_SCHED_AUTO = 0,          /* autotune at init over the others */
@@ -108,6 +116,12 @@ typedef struct {
   int warm_start;      /* 1: later Riemann problems of an interface start from the previous p* */
   int schedule;        /* GRPREC_SCHED_* (Euler) */
   int block;           /* workgroup size 64, 128 or 256 (0 = choose) */
+  int recon;           /* GRPREC_RECON_* */
+  double nl_lambda_c;  /* GRPrecNL weight of the centred polynomial, (0, 1e30]
+                          (default 10 when 0; the paper prints 1e9, with which
+                          GRPrecNL equals GRPrec on smooth data, while its GRPrecNL
+                          results are reproduced with 10) */
+  double nl_eps;       /* GRPrecNL epsilon, [1e-30, 1] (default 1e-14 when 0) */
 } grprec_problem;
 
 typedef struct {

@@ -309,9 +309,7 @@ int orc_side_matrix(int m, int side /* 0 = left, 1 = right */, double *M /* (m+1
  * cell i:  OI = sum_{l=1..m} integral over the cell of (d^l p/dx^l)^2 dx^(2l) dx,
  * the dx^(2l) factor as printed.  The integral is 5-point Gauss-Legendre,
  * exact here (the integrand has degree at most 6). */
-double orc_oi(int m, const double *c, double dx) {
-  double g[5], w[5];
-  orc_gauss_legendre(5, g, w);
+static double orc_oi_q(int m, const double *c, double dx, const double *g, const double *w) {
   double oi = 0.0;
   for (int l = 1; l <= m; ++l) {
     for (int k = 0; k < 5; ++k) {
@@ -328,11 +326,30 @@ double orc_oi(int m, const double *c, double dx) {
   return oi;
 }
 
+double orc_oi(int m, const double *c, double dx) {
+  double g[5], w[5];
+  orc_gauss_legendre(5, g, w);
+  return orc_oi_q(m, c, dx, g, w);
+}
+
+/* The matrices and quadrature nodes GRPrecNL needs for one degree. */
+typedef struct {
+  double RC[MAXN * 5], ML[MAXN * 7], MR[MAXN * 7];
+  double g5[5], w5[5];
+} orc_nl;
+
+static int orc_nl_init(int m, orc_nl *t) {
+  if (orc_recon_matrix(m, t->RC) || orc_side_matrix(m, 0, t->ML) || orc_side_matrix(m, 1, t->MR))
+    return ORC_E_INVALID;
+  return orc_gauss_legendre(5, t->g5, t->w5);
+}
+
 /* One scalar component: coefficients of beta_L p_L + beta_C p_C + beta_R p_R
  * and the three weights. */
-static void orc_nl_scalar(const orc_cfg *cf, double dx, const double *RC, const double *ML,
-                          const double *MR, const double *d, double *c, double *beta) {
+static void orc_nl_scalar(const orc_cfg *cf, double dx, const orc_nl *t, const double *d, double *c,
+                          double *beta) {
   int m = cf->m;
+  const double *RC = t->RC, *ML = t->ML, *MR = t->MR;
   double cl[MAXN], cc[MAXN], cr[MAXN];
   for (int r = 0; r <= m; ++r) {
     cl[r] = cc[r] = cr[r] = 0.0;
@@ -342,9 +359,9 @@ static void orc_nl_scalar(const orc_cfg *cf, double dx, const double *RC, const 
     }
     for (int k = 0; k < 5; ++k) cc[r] += RC[r * 5 + k] * d[k];
   }
-  double wl = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi(m, cl, dx), cf->nl_r);
-  double wc = cf->nl_lambda_c / pow(cf->nl_eps + orc_oi(m, cc, dx), cf->nl_r);
-  double wr = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi(m, cr, dx), cf->nl_r);
+  double wl = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi_q(m, cl, dx, t->g5, t->w5), cf->nl_r);
+  double wc = cf->nl_lambda_c / pow(cf->nl_eps + orc_oi_q(m, cc, dx, t->g5, t->w5), cf->nl_r);
+  double wr = ORC_NL_LAMBDA_SIDE / pow(cf->nl_eps + orc_oi_q(m, cr, dx, t->g5, t->w5), cf->nl_r);
   double ws = wl + wc + wr;
   double bl = wl / ws, bc = wc / ws, br = wr / ws;
   for (int r = 0; r <= m; ++r) c[r] = bl * cl[r] + bc * cc[r] + br * cr[r];
@@ -408,13 +425,11 @@ int orc_eigvec(double g, const double *Q, double *Rm) {
  * characteristic variables, Sec. 3.1), each characteristic field is
  * reconstructed as a scalar, and the result is projected back; beta then
  * refers to the characteristic fields. */
-int orc_recon_nl_cell(const orc_cfg *cf, double dx, const double *d, double *coef, double *beta) {
+static int orc_recon_nl_cell_t(const orc_cfg *cf, const orc_nl *t, double dx, const double *d,
+                               double *coef, double *beta) {
   int m = cf->m;
-  double RC[MAXN * 5], ML[MAXN * 7], MR[MAXN * 7];
-  if (orc_recon_matrix(m, RC) || orc_side_matrix(m, 0, ML) || orc_side_matrix(m, 1, MR))
-    return ORC_E_INVALID;
   if (cf->system == 0) {
-    orc_nl_scalar(cf, dx, RC, ML, MR, d, coef, beta);
+    orc_nl_scalar(cf, dx, t, d, coef, beta);
     return ORC_OK;
   }
   double Qbar[3] = {d[0 * 7 + 1], d[1 * 7 + 1], d[2 * 7 + 1]};
@@ -431,13 +446,19 @@ int orc_recon_nl_cell(const orc_cfg *cf, double dx, const double *d, double *coe
       w[k][j] = 0.0;
       for (int v = 0; v < 3; ++v) w[k][j] += Lm[k * 3 + v] * d[v * 7 + j];
     }
-  for (int k = 0; k < 3; ++k) orc_nl_scalar(cf, dx, RC, ML, MR, w[k], cw[k], beta ? beta + 3 * k : NULL);
+  for (int k = 0; k < 3; ++k) orc_nl_scalar(cf, dx, t, w[k], cw[k], beta ? beta + 3 * k : NULL);
   for (int v = 0; v < 3; ++v)
     for (int r = 0; r <= m; ++r) {
       coef[v * (m + 1) + r] = 0.0;
       for (int k = 0; k < 3; ++k) coef[v * (m + 1) + r] += Rm[v * 3 + k] * cw[k][r];
     }
   return ORC_OK;
+}
+
+int orc_recon_nl_cell(const orc_cfg *cf, double dx, const double *d, double *coef, double *beta) {
+  orc_nl t;
+  if (cf->m < 1 || cf->m > 4 || orc_nl_init(cf->m, &t)) return ORC_E_INVALID;
+  return orc_recon_nl_cell_t(cf, &t, dx, d, coef, beta);
 }
 
 /* ------------------------------------------------------------------ */
@@ -801,6 +822,8 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
   int per = (cf->bc_left == 0);
   double R[5 * 5];
   orc_recon_matrix(m, R);
+  orc_nl nlt;
+  if (cf->recon == 1) orc_nl_init(m, &nlt);
   orc_st s;
   orc_st_init(m, &s);
 
@@ -844,7 +867,7 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
       memcpy(d + vv * 7, dd, sizeof(dd));
     }
     if (cf->recon == 1) {
-      rc = orc_recon_nl_cell(cf, dx, d, coef, NULL);
+      rc = orc_recon_nl_cell_t(cf, &nlt, dx, d, coef, NULL);
       if (rc != ORC_OK) break;
     } else {
       for (int vv = 0; vv < nv; ++vv)

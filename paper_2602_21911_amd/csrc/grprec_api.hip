@@ -14,9 +14,9 @@
 
 namespace grp {
 // kernels.hip
-template <int M> hipError_t launch_euler(const EulerArgs<M> &, int, int, hipStream_t);
-template <int M> hipError_t euler_occupancy(int, int *);
-template <int M> hipError_t launch_adv(const AdvArgs<M> &, int, hipStream_t);
+template <int M> hipError_t launch_euler(const EulerArgs<M> &, int, int, bool, hipStream_t);
+template <int M> hipError_t euler_occupancy(int, bool, int *);
+template <int M> hipError_t launch_adv(const AdvArgs<M> &, int, bool, hipStream_t);
 hipError_t launch_init_interfaces_euler(double *, const double *, int, const Gas &, int, double, Ctl *,
                                         hipStream_t);
 hipError_t launch_init_interfaces_adv(double *, const double *, int, double, hipStream_t);
@@ -187,12 +187,12 @@ static std::vector<int4> build_tiles(grprec_handle *h, int schedule, int block) 
   return t;
 }
 
-static int euler_occ(int M, int block, int *occ) {
+static int euler_occ(int M, int block, bool nl, int *occ) {
   hipError_t e;
   switch (M) {
-    case 1: e = euler_occupancy<1>(block, occ); break;
-    case 2: e = euler_occupancy<2>(block, occ); break;
-    default: e = euler_occupancy<3>(block, occ); break;
+    case 1: e = euler_occupancy<1>(block, nl, occ); break;
+    case 2: e = euler_occupancy<2>(block, nl, occ); break;
+    default: e = euler_occupancy<3>(block, nl, occ); break;
   }
   return hip_fail(e);
 }
@@ -206,7 +206,7 @@ static int apply_schedule(grprec_handle *h, int schedule, int block) {
   h->schedule = schedule;
   h->block = block;
   int occ = 1;
-  int rc = euler_occ(h->M, block, &occ);
+  int rc = euler_occ(h->M, block, h->p.recon == GRPREC_RECON_NL, &occ);
   if (rc) return rc;
   if (occ < 1) occ = 1;
   long long g = (long long)occ * h->n_cu;
@@ -240,6 +240,8 @@ static EulerArgs<M> euler_args(const grprec_handle *h, int slot) {
   a.gate = h->p.mlp_gate;
   a.mlp = h->mlp;
   a.hv = h->hv;
+  a.nl_lambda_c = h->p.nl_lambda_c;
+  a.nl_eps = h->p.nl_eps;
   return a;
 }
 
@@ -254,6 +256,8 @@ static AdvArgs<M> adv_args(const grprec_handle *h, int slot) {
   a.periodic = h->p.bc == GRPREC_BC_PERIODIC;
   a.cfl = h->p.cfl;
   a.lambda = h->p.lambda;
+  a.nl_lambda_c = h->p.nl_lambda_c;
+  a.nl_eps = h->p.nl_eps;
   return a;
 }
 
@@ -264,7 +268,7 @@ static hipError_t launch_per_domain(grprec_handle *h, int slot, hipStream_t st) 
     const int t0 = h->dom_tile0[s], nt = h->dom_tile0[s + 1] - t0;
     a.tiles = h->tiles + t0;
     a.ntiles = nt;
-    hipError_t e = launch_euler<M>(a, h->block, nt, st);
+    hipError_t e = launch_euler<M>(a, h->block, nt, h->p.recon == GRPREC_RECON_NL, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -278,20 +282,21 @@ static hipError_t launch_step(grprec_handle *h, int slot, hipStream_t st) {
       default: return launch_per_domain<3>(h, slot, st);
     }
   }
+  const bool nl = h->p.recon == GRPREC_RECON_NL;
   if (h->p.system == GRPREC_EULER) {
     switch (h->M) {
-      case 1: return launch_euler<1>(euler_args<1>(h, slot), h->block, h->grid, st);
-      case 2: return launch_euler<2>(euler_args<2>(h, slot), h->block, h->grid, st);
-      default: return launch_euler<3>(euler_args<3>(h, slot), h->block, h->grid, st);
+      case 1: return launch_euler<1>(euler_args<1>(h, slot), h->block, h->grid, nl, st);
+      case 2: return launch_euler<2>(euler_args<2>(h, slot), h->block, h->grid, nl, st);
+      default: return launch_euler<3>(euler_args<3>(h, slot), h->block, h->grid, nl, st);
     }
   }
   long long g = (h->tc + 255) / 256;
   int grid = (int)std::max<long long>(1, std::min<long long>(g, 1 << 20));
   switch (h->M) {
-    case 1: return launch_adv<1>(adv_args<1>(h, slot), grid, st);
-    case 2: return launch_adv<2>(adv_args<2>(h, slot), grid, st);
-    case 3: return launch_adv<3>(adv_args<3>(h, slot), grid, st);
-    default: return launch_adv<4>(adv_args<4>(h, slot), grid, st);
+    case 1: return launch_adv<1>(adv_args<1>(h, slot), grid, nl, st);
+    case 2: return launch_adv<2>(adv_args<2>(h, slot), grid, nl, st);
+    case 3: return launch_adv<3>(adv_args<3>(h, slot), grid, nl, st);
+    default: return launch_adv<4>(adv_args<4>(h, slot), grid, nl, st);
   }
 }
 
@@ -408,6 +413,12 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (p.max_picard <= 0) p.max_picard = 64;
   if (!(p.picard_tol > 0.0)) p.picard_tol = 1e-13;
   if (p.mlp_gate == 0.0) p.mlp_gate = 0.1;
+  if (p.recon != GRPREC_RECON_LINEAR && p.recon != GRPREC_RECON_NL) return GRPREC_E_INVALID;
+  if (p.nl_lambda_c == 0.0) p.nl_lambda_c = 10.0;
+  if (p.nl_eps == 0.0) p.nl_eps = 1e-14;
+  // bounds that keep the weights' products of fourth powers inside double range
+  if (!(p.nl_lambda_c > 0.0 && p.nl_lambda_c <= 1e30)) return GRPREC_E_INVALID;
+  if (!(p.nl_eps >= 1e-30 && p.nl_eps <= 1.0)) return GRPREC_E_INVALID;
   if (p.guess == GRPREC_GUESS_MLP && !p.mlp_params) return GRPREC_E_INVALID;
   if (p.block != 0 && p.block != 64 && p.block != 128 && p.block != 256) return GRPREC_E_INVALID;
   if (p.schedule < GRPREC_SCHED_AUTO || p.schedule > GRPREC_SCHED_PER_DOMAIN) return GRPREC_E_INVALID;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "grprec_internal.h"
+#include "grprec_tables.h"
 
 namespace grp {
 
@@ -437,6 +438,103 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
   o.F[1] = r * u * u + p;
   o.F[2] = u * (E + p);
   return it > maxit ? ERR_NEWTON : 0u;
+}
+
+// ---------------------------------------------------------------- GRPrecNL
+// Nonlinear combination of the left, centred and right candidates for one
+// scalar field (Sec. 3.3).  aC: the centred (GRPrec) coefficients; del[k]:
+// datum k minus the cell mean (indices as in tab::NLTab; del[1] unused).
+// Indicators OI_k = dx a_k^T Gm a_k; weights omega_k = lambda_k/(eps+OI_k)^4
+// with lambda_L = lambda_R = 1, normalised.  Scaling every omega by the
+// product of the three (eps + OI)^4 leaves a single reciprocal:
+//   beta_L : beta_C : beta_R = sC sR : lambda_C sL sR : sL sC.
+template <int M>
+__device__ __forceinline__ void nl_mix(const double (&aC)[M], const double (&del)[7], double dx,
+                                       double lam_c, double eps, double (&out)[M]) {
+  constexpr tab::NLTab<M> T = tab::nl_tables<M>();
+  double aL[M], aR[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double l = 0.0, r = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      if (T.A[0][j][k] != 0.0) l = fma(T.A[0][j][k], del[T.sel[0][k]], l);
+      if (T.A[1][j][k] != 0.0) r = fma(T.A[1][j][k], del[T.sel[1][k]], r);
+    }
+    aL[j] = l;
+    aR[j] = r;
+  }
+  auto ind = [&](const double (&a)[M]) {
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double row = T.Gm[j][j] * a[j];
+#pragma unroll
+      for (int k = j + 1; k < M; ++k)
+        if (T.Gm[j][k] != 0.0) row = fma(2.0 * T.Gm[j][k], a[k], row);
+      sum = fma(row, a[j], sum);
+    }
+    double s = fma(dx, sum, eps);
+    s *= s;
+    return s * s;
+  };
+  const double sL = ind(aL), sC = ind(aC), sR = ind(aR);
+  const double wl = sC * sR, wc = lam_c * sL * sR, wr = sL * sC;
+  const double inv = rcp(wl + wc + wr);
+#pragma unroll
+  for (int j = 0; j < M; ++j) out[j] = (wl * aL[j] + wc * aC[j] + wr * aR[j]) * inv;
+}
+
+// Centred GRPrec coefficients (zero-mean basis) from data differences to the
+// cell mean: d0 = q_{i-1}, d2 = q_{i+1}, d3 = V_{i-1/2}, d4 = V_{i+1/2}, each
+// minus q_i (Sec. 3.1 closed forms).
+template <int M>
+__device__ __forceinline__ void grprec_from_diffs(double d0, double d2, double d3, double d4,
+                                                  double (&a)[M]) {
+  const double DI = d4 - d3, SI = d3 + d4;
+  if constexpr (M == 1) {
+    a[0] = DI;
+  } else if constexpr (M == 2) {
+    a[0] = DI;
+    a[1] = 3.0 * SI;
+  } else {
+    const double DC = d2 - d0, SC = d0 + d2;
+    a[0] = 1.25 * DI - 0.125 * DC;
+    a[2] = 0.5 * DC - DI;
+    if constexpr (M == 3) {
+      a[1] = (3.0 * SI + 18.0 * SC) * (1.0 / 37.0);
+    } else {
+      a[1] = 3.75 * SI - 0.125 * SC;
+      a[3] = (5.0 / 12.0) * SC - 2.5 * SI;
+    }
+  }
+}
+
+// Eigenvectors of the Euler flux Jacobian at a conserved state, for the
+// characteristic projection of the reconstruction (Sec. 3.1).  Right
+// eigenvectors (columns of Rm) for u - c, u, u + c:
+//   (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c);
+// rows of Lm = Rm^-1, with k = (g-1)/(2 c^2):
+//   (u^2 k/2 + u/(2c), -(u k + 1/(2c)), k), (1 - u^2 k, 2 u k, -2 k),
+//   (u^2 k/2 - u/(2c), -(u k - 1/(2c)), k).
+// A non-physical state gives NaN, which the later state checks report.
+__device__ __forceinline__ void euler_eigen(const Gas &G, const double (&Q)[3], double (&Lm)[3][3],
+                                            double (&Rm)[3][3]) {
+  const double ir = rcp(Q[0]);
+  const double u = Q[1] * ir;
+  const double p = G.gm1 * (Q[2] - 0.5 * Q[1] * u);
+  const double c = sqrtpos(G.g * p * ir);
+  const double ic = rcp(c), hic = 0.5 * ic;
+  const double k = 0.5 * G.gm1 * ic * ic;
+  const double H = (Q[2] + p) * ir;
+  const double uk = u * k, u2k = 0.5 * u * uk, uhic = u * hic;
+  Lm[0][0] = u2k + uhic; Lm[0][1] = -(uk + hic); Lm[0][2] = k;
+  Lm[1][0] = 1.0 - 2.0 * u2k; Lm[1][1] = 2.0 * uk; Lm[1][2] = -2.0 * k;
+  Lm[2][0] = u2k - uhic; Lm[2][1] = -(uk - hic); Lm[2][2] = k;
+  const double uc = u * c;
+  Rm[0][0] = 1.0; Rm[0][1] = 1.0; Rm[0][2] = 1.0;
+  Rm[1][0] = u - c; Rm[1][1] = u; Rm[1][2] = u + c;
+  Rm[2][0] = H - uc; Rm[2][1] = 0.5 * u * u; Rm[2][2] = H + uc;
 }
 
 }  // namespace grp

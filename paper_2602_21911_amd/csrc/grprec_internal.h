@@ -115,6 +115,7 @@ struct EulerArgs {
   double gate;
   const float *mlp;
   Harvest hv;
+  double nl_lambda_c, nl_eps;  // GRPrecNL weights (used by the NL instantiations)
 };
 
 template <int M>
@@ -126,6 +127,7 @@ struct AdvArgs {
   int slot;
   int periodic;
   double cfl, lambda;
+  double nl_lambda_c, nl_eps;  // GRPrecNL weights (used by the NL instantiations)
 };
 
 }  // namespace grp

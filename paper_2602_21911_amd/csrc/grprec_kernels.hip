@@ -78,7 +78,8 @@ __device__ __forceinline__ double pick(const double (&t)[N], int b) {
 #endif
 
 // AIR: gamma is 1.4 and the gas constants are compile-time values.
-template <int M, int B, bool AIR>
+// NL: GRPrecNL reconstruction (Sec. 3.3-3.4) instead of GRPrec (Sec. 3.1).
+template <int M, int B, bool AIR, bool NL>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES)))
 void euler_step(EulerArgs<M> a) {
   constexpr int N = M + 1;   // nodes per direction
@@ -165,6 +166,50 @@ void euler_step(EulerArgs<M> a) {
         if (ip >= n) ip = n - 1;
       }
       double w[3][N];
+      if constexpr (NL) {
+        // GRPrecNL in characteristic variables: differences of the stencil
+        // data to the cell mean are projected with the left eigenvectors at
+        // the cell mean, each field is reconstructed as a scalar, and the
+        // coefficients are projected back
+        double Lm[3][3], Rm[3][3];
+        euler_eigen(G, q0, Lm, Rm);
+        double dm[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0}, dl[3], dr[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          if constexpr (M >= 2) {
+            dm[v] = qin[v * tc + off + im] - q0[v];
+            dp[v] = qin[v * tc + off + ip] - q0[v];
+          }
+          dl[v] = vin[v * ti + io + i] - q0[v];
+          dr[v] = vin[v * ti + io + i + 1] - q0[v];
+        }
+        double ac[3][M];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          double del[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            del[0] = fma(Lm[f][v], dm[v], del[0]);
+            del[2] = fma(Lm[f][v], dp[v], del[2]);
+            del[3] = fma(Lm[f][v], dl[v], del[3]);
+            del[4] = fma(Lm[f][v], dr[v], del[4]);
+          }
+          double aC[M];
+          grprec_from_diffs<M>(del[0], del[2], del[3], del[4], aC);
+          nl_mix<M>(aC, del, dx, a.nl_lambda_c, a.nl_eps, ac[f]);
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          double cv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int j = 0; j < M; ++j)
+            cv[j] = Rm[v][0] * ac[0][j] + Rm[v][1] * ac[1][j] + Rm[v][2] * ac[2][j];
+#pragma unroll
+          for (int k = 0; k < N; ++k)
+            w[v][k] = q0[v] + cv[0] * T.phi[k][0] + cv[1] * T.phi[k][1] + cv[2] * T.phi[k][2] +
+                      cv[3] * T.phi[k][3];
+        }
+      } else {
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         const double qc = q0[v];
@@ -192,6 +237,7 @@ void euler_step(EulerArgs<M> a) {
         for (int k = 0; k < N; ++k)
           w[v][k] = qc + a1 * T.phi[k][0] + a2 * T.phi[k][1] + a3 * T.phi[k][2] +
                     a4 * T.phi[k][3];
+      }
       }
       // Picard iteration of the space-time Galerkin equations
       double qh[3][N][N];
@@ -453,6 +499,21 @@ __device__ __forceinline__ void basis_mean(double lo, double hi, double K[4]) {
   for (int j = 0; j < 4; ++j) K[j] = (Bv[j] - A[j]) * inv;
 }
 
+// GRPrecNL coefficients of one cell (Sec. 3.3-3.4) from its seven data
+// (vll = V_{i-3/2}, vrr = V_{i+3/2}; read at degree 4 only).
+template <int M>
+__device__ __forceinline__ void adv_coeffs_nl(double qm, double qc, double qp, double vl, double vr,
+                                              double vll, double vrr, double dx, double lam_c,
+                                              double eps, double a[4]) {
+  const double del[7] = {qm - qc, 0.0, qp - qc, vl - qc, vr - qc, vll - qc, vrr - qc};
+  double aC[M], o[M];
+  grprec_from_diffs<M>(del[0], del[2], del[3], del[4], aC);
+  nl_mix<M>(aC, del, dx, lam_c, eps, o);
+  a[0] = a[1] = a[2] = a[3] = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) a[j] = o[j];
+}
+
 template <int M>
 __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, double vl, double vr,
                                            double a[4]) {
@@ -480,7 +541,7 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
 #define ADV_CELLS_PER_THREAD 2
 #endif
 
-template <int M>
+template <int M, bool NL>
 __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   Ctl *ctl = a.ctl;
   const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
@@ -555,9 +616,27 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       }
       return vin[k];
     };
+    // coefficients of cell k's polynomial; GRPrecNL at degree 4 also reads
+    // V_{k-3/2} and V_{k+3/2}, which beyond a transmissive end belong to the
+    // ghost cell (its constant average)
+    auto coeffs = [&](int k, double qk, double out[4]) {
+      if constexpr (NL) {
+        auto VG = [&](int j) -> double {
+          if (!a.periodic) {
+            if (j < 0) return qin[0];
+            if (j > n) return qin[n - 1];
+          }
+          return V(j);
+        };
+        adv_coeffs_nl<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), M == 4 ? VG(k - 1) : 0.0,
+                         M == 4 ? VG(k + 2) : 0.0, dx, a.nl_lambda_c, a.nl_eps, out);
+      } else {
+        adv_coeffs<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), out);
+      }
+    };
     double ac[4], au[4];
     const double qc = qin[i];
-    adv_coeffs<M>(Q(i - 1), qc, Q(i + 1), V(i), V(i + 1), ac);
+    coeffs(i, qc, ac);
     double mean_self = qc, pt_self = qc;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -573,7 +652,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
         pt_up = qc;
       } else {
         const double qu = Q(i - 1);
-        adv_coeffs<M>(Q(i - 2), qu, qc, V(i - 1), V(i), au);
+        coeffs(i - 1, qu, au);
         mean_up = qu;
         pt_up = qu;
 #pragma unroll
@@ -592,7 +671,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
         pt_up = qc;
       } else {
         const double qu = Q(i + 1);
-        adv_coeffs<M>(qc, qu, Q(i + 2), V(i + 1), V(i + 2), au);
+        coeffs(i + 1, qu, au);
         mean_up = qu;
         pt_up = qu;
 #pragma unroll
@@ -727,55 +806,69 @@ __global__ void digest(const double *x, long long n, Ctl *ctl) {
 
 // ============================================================ launchers
 // (host-callable wrappers so that the API file needs no kernel templates)
-template <int M, int B>
-static hipError_t launch_euler_mb(const EulerArgs<M> &a, int grid, hipStream_t st) {
+template <int M, int B, bool NL>
+static hipError_t launch_euler_mbn(const EulerArgs<M> &a, int grid, hipStream_t st) {
   if (a.gas.g == kGammaAir)
-    hipLaunchKernelGGL((euler_step<M, B, true>), dim3(grid), dim3(B), 0, st, a);
+    hipLaunchKernelGGL((euler_step<M, B, true, NL>), dim3(grid), dim3(B), 0, st, a);
   else
-    hipLaunchKernelGGL((euler_step<M, B, false>), dim3(grid), dim3(B), 0, st, a);
+    hipLaunchKernelGGL((euler_step<M, B, false, NL>), dim3(grid), dim3(B), 0, st, a);
   return hipGetLastError();
 }
 
+template <int M, int B>
+static hipError_t launch_euler_mb(const EulerArgs<M> &a, int grid, bool nl, hipStream_t st) {
+  return nl ? launch_euler_mbn<M, B, true>(a, grid, st) : launch_euler_mbn<M, B, false>(a, grid, st);
+}
+
 template <int M>
-hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, hipStream_t st) {
+hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, bool nl, hipStream_t st) {
   switch (block) {
-    case 64: return launch_euler_mb<M, 64>(a, grid, st);
-    case 128: return launch_euler_mb<M, 128>(a, grid, st);
-    case 256: return launch_euler_mb<M, 256>(a, grid, st);
+    case 64: return launch_euler_mb<M, 64>(a, grid, nl, st);
+    case 128: return launch_euler_mb<M, 128>(a, grid, nl, st);
+    case 256: return launch_euler_mb<M, 256>(a, grid, nl, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int M, int B>
+static hipError_t euler_occ_b(bool nl, int *blocks_per_cu) {
+  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true>, B, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false>, B, 0);
+}
+
+template <int M>
+hipError_t euler_occupancy(int block, bool nl, int *blocks_per_cu) {
+  switch (block) {
+    case 64: return euler_occ_b<M, 64>(nl, blocks_per_cu);
+    case 128: return euler_occ_b<M, 128>(nl, blocks_per_cu);
+    case 256: return euler_occ_b<M, 256>(nl, blocks_per_cu);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int M>
-hipError_t euler_occupancy(int block, int *blocks_per_cu) {
-  switch (block) {
-    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 64, true>, 64, 0);
-    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 128, true>, 128, 0);
-    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, 256, true>, 256, 0);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int M>
-hipError_t launch_adv(const AdvArgs<M> &a, int grid, hipStream_t st) {
+hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
   (void)grid;
   const long long ch = ADV_CELLS_PER_THREAD * 256LL;
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
-  hipLaunchKernelGGL((adv_step<M>), dim3(g), dim3(256), 0, st, a);
+  if (nl)
+    hipLaunchKernelGGL((adv_step<M, true>), dim3(g), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((adv_step<M, false>), dim3(g), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_euler<1>(const EulerArgs<1> &, int, int, hipStream_t);
-template hipError_t launch_euler<2>(const EulerArgs<2> &, int, int, hipStream_t);
-template hipError_t launch_euler<3>(const EulerArgs<3> &, int, int, hipStream_t);
-template hipError_t euler_occupancy<1>(int, int *);
-template hipError_t euler_occupancy<2>(int, int *);
-template hipError_t euler_occupancy<3>(int, int *);
-template hipError_t launch_adv<1>(const AdvArgs<1> &, int, hipStream_t);
-template hipError_t launch_adv<2>(const AdvArgs<2> &, int, hipStream_t);
-template hipError_t launch_adv<3>(const AdvArgs<3> &, int, hipStream_t);
-template hipError_t launch_adv<4>(const AdvArgs<4> &, int, hipStream_t);
+template hipError_t launch_euler<1>(const EulerArgs<1> &, int, int, bool, hipStream_t);
+template hipError_t launch_euler<2>(const EulerArgs<2> &, int, int, bool, hipStream_t);
+template hipError_t launch_euler<3>(const EulerArgs<3> &, int, int, bool, hipStream_t);
+template hipError_t euler_occupancy<1>(int, bool, int *);
+template hipError_t euler_occupancy<2>(int, bool, int *);
+template hipError_t euler_occupancy<3>(int, bool, int *);
+template hipError_t launch_adv<1>(const AdvArgs<1> &, int, bool, hipStream_t);
+template hipError_t launch_adv<2>(const AdvArgs<2> &, int, bool, hipStream_t);
+template hipError_t launch_adv<3>(const AdvArgs<3> &, int, bool, hipStream_t);
+template hipError_t launch_adv<4>(const AdvArgs<4> &, int, bool, hipStream_t);
 
 hipError_t launch_init_interfaces_euler(double *v0, const double *v1, int ti, const Gas &G, int maxit,
                                         double tol, Ctl *ctl, hipStream_t st) {

@@ -142,5 +142,101 @@ constexpr Predictor<M> predictor() {
   return P;
 }
 
+// ---------------------------------------------------------------- GRPrecNL
+// Candidate polynomials of the nonlinear reconstruction (Sec. 3.3-3.4) in the
+// zero-mean basis phi_1..phi_M of cell i (xi in [-1/2, 1/2]):
+//   p = q_i + sum_j a_j phi_j,  a = A (d_sel - q_i),
+// where d_sel are the data each candidate interpolates besides the mean of
+// cell i, indexed 0 = mean of cell i-1, 2 = mean of cell i+1, 3 = value at
+// xi = -1/2, 4 = at +1/2, 5 = at -3/2, 6 = at +3/2:
+//   degree 1: left {3},          right {4}
+//   degree 2: left {0, 4},       right {2, 3}
+//   degree 3: left {0, 2, 3},    right {0, 2, 4}
+//   degree 4: left {0, 2, 3, 5}, right {0, 2, 4, 6}.
+// The oscillation indicator of a candidate is dx * a^T Gm a with
+// Gm[j][k] = sum_l int_{-1/2}^{1/2} phi_j^(l) phi_k^(l) dxi.
+constexpr double phi_at(int j, double x) {  // phi_{j+1}(x)
+  const double x2 = x * x;
+  return j == 0 ? x : j == 1 ? x2 - 1.0 / 12.0 : j == 2 ? x2 * x : x2 * x2 - 1.0 / 80.0;
+}
+constexpr double phi_prim(int j, double x) {  // an antiderivative of phi_{j+1}
+  const double x2 = x * x;
+  return j == 0 ? 0.5 * x2
+       : j == 1 ? x2 * x / 3.0 - x / 12.0
+       : j == 2 ? 0.25 * x2 * x2
+                : 0.2 * x2 * x2 * x - x / 80.0;
+}
+constexpr double nl_functional(int cond, int j) {
+  switch (cond) {
+    case 0: return phi_prim(j, -0.5) - phi_prim(j, -1.5);  // mean over a unit cell
+    case 2: return phi_prim(j, 1.5) - phi_prim(j, 0.5);
+    case 3: return phi_at(j, -0.5);
+    case 4: return phi_at(j, 0.5);
+    case 5: return phi_at(j, -1.5);
+    default: return phi_at(j, 1.5);
+  }
+}
+constexpr double cfact(int n, int l) {  // n! / (n-l)!
+  double r = 1.0;
+  for (int t = 0; t < l; ++t) r *= (double)(n - t);
+  return r;
+}
+constexpr double mono_int(int p) {  // int_{-1/2}^{1/2} xi^p dxi
+  if (p % 2) return 0.0;
+  double h = 1.0;
+  for (int t = 0; t <= p; ++t) h *= 0.5;
+  return 2.0 * h / (p + 1.0);
+}
+
+template <int M>
+struct NLTab {
+  int sel[2][M];        // [left/right][condition]
+  double A[2][M][M];    // a = A (d_sel - q_i)
+  double Gm[M][M];
+};
+
+template <int M>
+constexpr NLTab<M> nl_tables() {
+  NLTab<M> T{};
+  const int sets[4][2][4] = {{{3}, {4}}, {{0, 4}, {2, 3}}, {{0, 2, 3}, {0, 2, 4}},
+                             {{0, 2, 3, 5}, {0, 2, 4, 6}}};
+  for (int side = 0; side < 2; ++side) {
+    double K[M][2 * M] = {};
+    for (int r = 0; r < M; ++r) {
+      T.sel[side][r] = sets[M - 1][side][r];
+      for (int j = 0; j < M; ++j) K[r][j] = nl_functional(T.sel[side][r], j);
+      K[r][M + r] = 1.0;
+    }
+    for (int col = 0; col < M; ++col) {  // Gauss-Jordan with partial pivoting
+      int piv = col;
+      for (int r = col + 1; r < M; ++r)
+        if (cabs(K[r][col]) > cabs(K[piv][col])) piv = r;
+      for (int k = 0; k < 2 * M; ++k) {
+        double t = K[col][k];
+        K[col][k] = K[piv][k];
+        K[piv][k] = t;
+      }
+      const double d = K[col][col];
+      for (int k = 0; k < 2 * M; ++k) K[col][k] /= d;
+      for (int r = 0; r < M; ++r) {
+        if (r == col) continue;
+        const double f = K[r][col];
+        for (int k = 0; k < 2 * M; ++k) K[r][k] -= f * K[col][k];
+      }
+    }
+    for (int j = 0; j < M; ++j)
+      for (int r = 0; r < M; ++r) T.A[side][j][r] = K[j][M + r];
+  }
+  // phi_j^(l) = (j+1)!/(j+1-l)! xi^(j+1-l) for l >= 1 (constants drop out)
+  for (int j = 0; j < M; ++j)
+    for (int k = 0; k < M; ++k) {
+      double g = 0.0;
+      for (int l = 1; l <= (j < k ? j : k) + 1; ++l)
+        g += cfact(j + 1, l) * cfact(k + 1, l) * mono_int(j + k + 2 - 2 * l);
+      T.Gm[j][k] = g;
+    }
+  return T;
+}
+
 }  // namespace tab
 }  // namespace grp
