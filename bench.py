@@ -156,10 +156,11 @@ def bench_network(args, G, torch, params):
     return out
 
 
-def bench_advection(G, torch, n, order=3, steps=200, warmup=20):
+def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0):
     from paper_2602_21911_amd import inputs as I
     dx, q, vl, vr = I.adv_sin2pi(n)
-    sim = G.Simulation(G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
+    sim = G.Simulation(G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC,
+                       recon=recon)
     try:
         sim.run(1e9, warmup)
         sec, _ = timed_run(sim, steps, torch)
@@ -167,9 +168,66 @@ def bench_advection(G, torch, n, order=3, steps=200, warmup=20):
         sim.close()
     per = sec / steps
     gbs = BYTES_ADV * n / per / 1e9
-    traffic = traffic_from_profiles("adv_step_order3_2e25", n) if (n == 1 << 25 and order == 3) else None
-    return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per, "hbm_gbs": gbs,
-            "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm", "traffic": traffic}
+    key = "adv_step_order%d_2e25%s" % (order, "_nl" if recon else "")
+    traffic = traffic_from_profiles(key, n) if n == 1 << 25 else None
+    return {"cells": n, "order": order, "recon": "GRPrecNL" if recon else "GRPrec", "rate": n / per,
+            "ms_per_step": 1e3 * per, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm",
+            "traffic": traffic}
+
+
+def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon):
+    """Rate of one batched form, and its solver counters over the same steps
+    (counted in a second, untimed run)."""
+    cells = int(net.n_cells.sum())
+    kw = dict(bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params, schedule=schedule,
+              block=block, recon=recon)
+    sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr, **kw)
+    try:
+        sched, blk = G.grprec_get_schedule(sim.h)
+        sim.run(1e9, warmup)
+        sec, _ = timed_run(sim, steps, torch)
+    finally:
+        sim.close()
+    kw.update(schedule=sched, block=blk)
+    sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr, **kw)
+    try:
+        G.grprec_enable_stats(sim.h, True)
+        sim.run(1e9, warmup + steps)
+        st = G.grprec_get_stats(sim.h)
+    finally:
+        sim.close()
+    rs = max(1, st["rs_calls"])
+    return {"rate": cells * steps / sec, "ms_per_step": 1e3 * sec / steps, "schedule": sched,
+            "block": blk, "newton_per_rs": st["newton_iters"] / rs,
+            "mlp_starts_per_rs": st["mlp_guesses"] / rs,
+            "sweeps_per_cell": st["picard_sweeps"] / max(1, st["cells_predicted"])}
+
+
+def bench_tube_network(G, torch, params, steps=100, warmup=10):
+    """10^4 shock tubes (GRPrecNL, order 3): the discontinuous workload on
+    which the learned Newton start can matter; PVRS vs learned start, same
+    schedule."""
+    from paper_2602_21911_amd import inputs as I
+    net = I.tube_network(n_seg=10000, seed=I.SEED_TUBE_NETWORK)
+    out = {"workload": "10000 shock tubes, GRPrecNL order 3, cells uniform [20,200) (seed %d), rho and p"
+                       " ratios up to 2, |u| <= 0.1, transmissive" % I.SEED_TUBE_NETWORK,
+           "cells": int(net.n_cells.sum())}
+    first = G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS
+    a = _network_form(G, torch, net, first, params, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1)
+    out["batched_mlp" if params is not None else "batched_pvrs"] = a
+    if params is not None:
+        out["batched_pvrs"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, a["schedule"],
+                                            a["block"], steps, warmup, 1)
+    return out
+
+
+def bench_network_nl(G, torch, steps=100, warmup=10):
+    """The headline network with GRPrecNL instead of GRPrec (PVRS start)."""
+    from paper_2602_21911_amd import inputs as I
+    net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
+    r = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1)
+    r["cells"] = int(net.n_cells.sum())
+    return r
 
 
 def bench_euler_single(G, torch, n, order=3, steps=50, warmup=5):
@@ -264,7 +322,10 @@ def main():
     torch.cuda.set_device(0)
     G.lib()
     if args.only == "advection":
-        out = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25)]
+        out = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25),
+               bench_advection(G, torch, 1 << 25, order=5),
+               bench_advection(G, torch, 1 << 25, recon=1),
+               bench_advection(G, torch, 1 << 25, order=5, recon=1)]
         print(json.dumps({"advection": out}), flush=True)
         return
     if args.only == "counters":
@@ -321,8 +382,13 @@ def main():
     if mlp is not None:
         line["mlp"] = mlp
     if not args.no_extras:
-        line["advection"] = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25)]
+        line["advection"] = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25),
+                             bench_advection(G, torch, 1 << 25, order=5),
+                             bench_advection(G, torch, 1 << 25, recon=1),
+                             bench_advection(G, torch, 1 << 25, order=5, recon=1)]
         line["euler_single_domain"] = bench_euler_single(G, torch, 1 << 22)
+        line["network_grprecnl"] = bench_network_nl(G, torch)
+        line["tube_network"] = bench_tube_network(G, torch, params)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -112,8 +112,12 @@ typedef struct {
   int max_picard;      /* predictor sweep cap (default 64 when 0) */
   double picard_tol;   /* predictor stop: max|change| <= tol (1 + max|q|) (default 1e-13) */
   const float *mlp_params; /* device, GRPREC_MLP_NPARAMS floats; needed for GUESS_MLP */
-  double mlp_gate;     /* learned guess used when the relative jump exceeds this (default 0.1) */
-  int warm_start;      /* 1: later Riemann problems of an interface start from the previous p* */
+  double mlp_gate;     /* relative data jump |dp|/pbar + |drho|/rhobar + |du|/cbar of an
+                          interface's first Riemann problem above which the learned and
+                          warm starts are taken; below it Newton starts from PVRS
+                          (default 0.1; negative: always) */
+  int warm_start;      /* 1: at interfaces above the gate, later Riemann problems start
+                          from the previous time's p* (implied by GUESS_MLP) */
   int schedule;        /* GRPREC_SCHED_* (Euler) */
   int block;           /* workgroup size 64, 128 or 256 (0 = choose) */
   int recon;           /* GRPREC_RECON_* */

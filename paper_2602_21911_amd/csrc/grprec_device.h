@@ -391,12 +391,16 @@ struct RSOut {
   int iters;
 };
 
-// With mlp != nullptr and no positive pguess, the start is start_pressure()'s
-// (learned where the jump passes the gate); `used` reports that choice.
+// Start of the Newton iteration: pguess when positive, else PVRS.  With
+// strong != nullptr the data jump is first tested against the gate and the
+// result stored there; below the gate Newton starts from PVRS (already
+// accurate to second order in the jump for weak waves), above it from the
+// learned proposal when mlp != nullptr (`used` reports that), else from
+// pguess when positive.
 __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], const double QR[3],
                                              double pguess, int maxit, double tol, RSOut &o,
                                              const float *mlp = nullptr, double gate = 0.0,
-                                             bool *used = nullptr) {
+                                             bool *used = nullptr, bool *strong = nullptr) {
   Prim L, R;
   bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
   bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
@@ -413,16 +417,19 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
     o.pstar = 0.0;
     return ERR_VACUUM;
   }
-  double p0;
-  if (pguess > 0.0) {
-    p0 = pguess;
-  } else if (mlp != nullptr) {
-    bool u;
-    p0 = start_pressure(G, L, R, 1, gate, mlp, u);
-    *used = u;
+  double p0 = 0.0;
+  if (strong != nullptr) {
+    *strong = jump_exceeds(L, R, gate);
+    if (*strong && mlp != nullptr) {
+      p0 = learned_pressure(G, L, R, mlp);
+      if (p0 > 0.0) *used = true;
+    } else if (*strong) {
+      p0 = pguess;
+    }
   } else {
-    p0 = pvrs(L, R);
+    p0 = pguess;
   }
+  if (!(p0 > 0.0)) p0 = pvrs(L, R);
   double ps, us;
   Side sl, sr;
   int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us, sl, sr);

@@ -326,7 +326,9 @@ void euler_step(EulerArgs<M> a) {
     double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
     if (work && (useful || e == 0)) {
       const bool boundary = (!a.periodic) && (i == n - 1);
+      const bool gated = a.warm || a.guess == 1;
       double pw = 0.0;
+      bool strong = false;
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
@@ -336,13 +338,15 @@ void euler_step(EulerArgs<M> a) {
         } else {
           QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
         }
-        // first time: PVRS or the learned start; later times start from the
-        // previous time's star pressure when warm starts are on
-        const bool warm = b > 0 && (a.warm || a.guess == 1);
+        // the first time tests the interface's jump against the gate; above
+        // it the first time starts from the learned proposal and later times
+        // from the previous time's star pressure, below it (and without
+        // either option) every time starts from PVRS
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         bool used = false;
         RSOut o;
-        err |= interact(G, QL, QR, warm ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp, a.gate, &used);
+        err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
+                        a.gate, &used, (b == 0 && gated) ? &strong : nullptr);
         st_mlp += used ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
@@ -379,15 +383,17 @@ void euler_step(EulerArgs<M> a) {
     // left end of a transmissive domain: ghost average against the left trace
     double FL[3] = {0.0, 0.0, 0.0}, VL[3] = {0.0, 0.0, 0.0};
     if (work && useful && i == 0 && !a.periodic) {
+      const bool gated = a.warm || a.guess == 1;
       double pw = 0.0;
+      bool strong = false;
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
-        const bool warm = b > 0 && (a.warm || a.guess == 1);
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         bool used = false;
         RSOut o;
-        err |= interact(G, q0, QR, warm ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp, a.gate, &used);
+        err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
+                        a.gate, &used, (b == 0 && gated) ? &strong : nullptr);
         st_mlp += used ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
@@ -537,9 +543,10 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
   }
 }
 
-#ifndef ADV_CELLS_PER_THREAD
-#define ADV_CELLS_PER_THREAD 2
+#ifndef ADV_PASSES
+#define ADV_PASSES 2  // runs per wave per block chunk
 #endif
+#define ADV_RUN 63    // cells a wave updates per run (64 lanes, one upwind overlap)
 
 template <int M, bool NL>
 __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
@@ -579,110 +586,108 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     basis_mean(-0.5, -0.5 - cn, Kin);
     basis_at(-0.5 - cn, Pin);
   }
-  // Each block takes contiguous chunks of ADV_CELLS_PER_THREAD * 256 cells.
-  // Blocks are dispatched to the 8 XCDs round-robin, so block b works on
-  // chunk (b % 8) * per + b / 8: consecutive chunks run on one XCD and the
-  // cache lines they share at their ends are read once through its L2.
-  constexpr int CH = ADV_CELLS_PER_THREAD * 256;
+  auto Q = [&](int k) -> double {
+    if (a.periodic) {
+      if (k < 0) k += n;
+      if (k >= n) k -= n;
+    } else {
+      if (k < 0) k = 0;
+      if (k >= n) k = n - 1;
+    }
+    return qin[k];
+  };
+  auto V = [&](int k) -> double {  // interface index 0..n
+    if (a.periodic) {
+      if (k < 0) k += n;
+      if (k > n) k -= n;
+    }
+    return vin[k];
+  };
+  // coefficients of cell k's polynomial; GRPrecNL at degree 4 also reads
+  // V_{k-3/2} and V_{k+3/2}, which beyond a transmissive end belong to the
+  // ghost cell (its constant average)
+  auto coeffs = [&](int k, double qk, double out[4]) {
+    if constexpr (NL) {
+      auto VG = [&](int j) -> double {
+        if (!a.periodic) {
+          if (j < 0) return qin[0];
+          if (j > n) return qin[n - 1];
+        }
+        return V(j);
+      };
+      adv_coeffs_nl<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), M == 4 ? VG(k - 1) : 0.0,
+                       M == 4 ? VG(k + 2) : 0.0, dx, a.nl_lambda_c, a.nl_eps, out);
+    } else {
+      adv_coeffs<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), out);
+    }
+  };
+  // A wave advances runs of ADV_RUN = 63 consecutive cells.  Its 64th lane
+  // holds the run's upwind neighbour (lane 0 for lambda > 0, lane 63 for
+  // lambda < 0), so every lane reconstructs one cell and the upwind lane's
+  // flux mean and end-of-step datum reach the next lane by a shuffle.  A block
+  // takes chunks of 4 waves x ADV_PASSES runs.  Blocks are dispatched to the 8
+  // XCDs round-robin, so block b works on chunk (b % 8) * per + b / 8:
+  // consecutive chunks run on one XCD and the cache lines they share at their
+  // ends are read once through its L2.
+  constexpr int RUN = ADV_RUN;
+  constexpr int CH = 4 * ADV_PASSES * RUN;
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
   const int nch = (n + CH - 1) / CH;
   const int per = (nch + 7) / 8;
   for (int blk = blockIdx.x; blk < 8 * per; blk += gridDim.x) {
   const int chunk = (blk % 8) * per + blk / 8;
   if (chunk >= nch) continue;
 #pragma unroll
-  for (int sub = 0; sub < ADV_CELLS_PER_THREAD; ++sub) {
-    const int i = chunk * CH + sub * 256 + (int)threadIdx.x;
-    if (i >= n) break;
+  for (int r = 0; r < ADV_PASSES; ++r) {
+    const int base = chunk * CH + (r * 4 + wave) * RUN;  // first cell the run updates
+    if (base >= n) break;                                 // uniform over the wave
+    const int i = pos ? base + lane - 1 : base + lane;    // this lane's cell
+    const bool own = pos ? lane >= 1 : lane < RUN;        // updated by this run
+    // the lane's flux mean over the swept interval and its datum; at i = -1
+    // and i = n the upwind neighbour is the periodic image or the ghost cell
+    // (a constant state: mean and point value are the end average)
+    double mean_s = 0.0, pt_s = 0.0;
+    int k = -1;
+    if (i >= 0 && i < n) {
+      k = i;
+    } else if (i == -1 || i == n) {
+      if (a.periodic) {
+        k = i < 0 ? n - 1 : 0;
+      } else {
+        mean_s = pt_s = qin[i < 0 ? 0 : n - 1];
+      }
+    }
+    if (k >= 0 && !done) {
+      const double qk = qin[k];
+      double ac[4];
+      coeffs(k, qk, ac);
+      mean_s = qk;
+      pt_s = qk;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        mean_s += ac[j] * Kin[j];
+        pt_s += ac[j] * Pin[j];
+      }
+    }
+    const double mean_u = pos ? __shfl_up(mean_s, 1, 64) : __shfl_down(mean_s, 1, 64);
+    const double pt_u = pos ? __shfl_up(pt_s, 1, 64) : __shfl_down(pt_s, 1, 64);
+    if (!own || i < 0 || i >= n) continue;
     if (done) {
       qout[i] = qin[i];
       vout[i] = vin[i];
       if (i == n - 1) vout[n] = vin[n];
       continue;
     }
-    auto Q = [&](int k) -> double {
-      if (a.periodic) {
-        if (k < 0) k += n;
-        if (k >= n) k -= n;
-      } else {
-        if (k < 0) k = 0;
-        if (k >= n) k = n - 1;
-      }
-      return qin[k];
-    };
-    auto V = [&](int k) -> double {  // interface index 0..n
-      if (a.periodic) {
-        if (k < 0) k += n;
-        if (k > n) k -= n;
-      }
-      return vin[k];
-    };
-    // coefficients of cell k's polynomial; GRPrecNL at degree 4 also reads
-    // V_{k-3/2} and V_{k+3/2}, which beyond a transmissive end belong to the
-    // ghost cell (its constant average)
-    auto coeffs = [&](int k, double qk, double out[4]) {
-      if constexpr (NL) {
-        auto VG = [&](int j) -> double {
-          if (!a.periodic) {
-            if (j < 0) return qin[0];
-            if (j > n) return qin[n - 1];
-          }
-          return V(j);
-        };
-        adv_coeffs_nl<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), M == 4 ? VG(k - 1) : 0.0,
-                         M == 4 ? VG(k + 2) : 0.0, dx, a.nl_lambda_c, a.nl_eps, out);
-      } else {
-        adv_coeffs<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), out);
-      }
-    };
-    double ac[4], au[4];
     const double qc = qin[i];
-    coeffs(i, qc, ac);
-    double mean_self = qc, pt_self = qc;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      mean_self += ac[j] * Kin[j];
-      pt_self += ac[j] * Pin[j];
-    }
     double qn;
     if (pos) {
-      // upwind neighbour i-1 supplies the left interface
-      double mean_up, pt_up;
-      if (i == 0 && !a.periodic) {  // inflow: ghost cell holding this cell's average
-        mean_up = qc;
-        pt_up = qc;
-      } else {
-        const double qu = Q(i - 1);
-        coeffs(i - 1, qu, au);
-        mean_up = qu;
-        pt_up = qu;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          mean_up += au[j] * Kin[j];
-          pt_up += au[j] * Pin[j];
-        }
-      }
-      qn = qc - cn * (mean_self - mean_up);
-      vout[i + 1] = pt_self;
-      if (i == 0) vout[0] = pt_up;
+      qn = qc - cn * (mean_s - mean_u);
+      vout[i + 1] = pt_s;
+      if (i == 0) vout[0] = pt_u;
     } else {
-      double mean_up, pt_up;
-      if (i == n - 1 && !a.periodic) {  // inflow from the right: ghost average
-        mean_up = qc;
-        pt_up = qc;
-      } else {
-        const double qu = Q(i + 1);
-        coeffs(i + 1, qu, au);
-        mean_up = qu;
-        pt_up = qu;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          mean_up += au[j] * Kin[j];
-          pt_up += au[j] * Pin[j];
-        }
-      }
-      qn = qc - cn * (mean_up - mean_self);
-      vout[i] = pt_self;
-      if (i == n - 1) vout[n] = pt_up;
+      qn = qc - cn * (mean_u - mean_s);
+      vout[i] = pt_s;
+      if (i == n - 1) vout[n] = pt_u;
     }
     qout[i] = qn;
     if (!isfinite(qn)) atomicOr(&ctl->err, ERR_NONPHYS);
@@ -849,7 +854,7 @@ hipError_t euler_occupancy(int block, bool nl, int *blocks_per_cu) {
 template <int M>
 hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
   (void)grid;
-  const long long ch = ADV_CELLS_PER_THREAD * 256LL;
+  const long long ch = 4LL * ADV_PASSES * ADV_RUN;
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
   if (nl)

@@ -27,6 +27,7 @@ import numpy as np
 SEED_NETWORK = 20260221
 SEED_TUBES_TRAIN = 20260222
 SEED_TUBES_HELDOUT = 20260223
+SEED_TUBE_NETWORK = 20260224
 
 
 def grid(n: int, x0: float = 0.0, length: float = 1.0):
@@ -188,3 +189,44 @@ def network(n_seg=10000, seed=SEED_NETWORK, nmin=3, nmax=2000, lmin=0.01, lmax=1
     q = prim_to_cons(rho_c, u, p, gamma)
     v = prim_to_cons(rho_f, u, p, gamma)
     return Network(n_cells, lengths, wavenum, cell_off, dx, q, v, v.copy())
+
+
+def tube_network(n_seg=10000, seed=SEED_TUBE_NETWORK, nmin=20, nmax=200, ratio=2.0, du=0.1,
+                 gamma=1.4) -> Network:
+    """Independent shock tubes of unit length: n_s uniform integer in
+    [nmin, nmax), the jump at interface n_s // 2; left state rho, p
+    log-uniform [0.5, 2], right state rho and p the left ones times
+    exp(U[-ln ratio, ln ratio]), u_L and u_R uniform [-du, du].  At the jump
+    the left (right) interface limit is the left (right) state."""
+    rng = np.random.default_rng(seed)
+    n_cells = rng.integers(nmin, nmax, n_seg).astype(np.int64)
+    lr = np.log(ratio)
+    rl = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_seg))
+    pl = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_seg))
+    rr = rl * np.exp(rng.uniform(-lr, lr, n_seg))
+    pr = pl * np.exp(rng.uniform(-lr, lr, n_seg))
+    ul = rng.uniform(-du, du, n_seg)
+    ur = rng.uniform(-du, du, n_seg)
+    lengths = np.ones(n_seg)
+    cell_off = np.zeros(n_seg + 1, dtype=np.int64)
+    cell_off[1:] = np.cumsum(n_cells)
+    total = int(cell_off[-1])
+    dx = lengths / n_cells
+    W = np.empty((3, total))
+    WL = np.empty((3, total + n_seg))
+    WR = np.empty((3, total + n_seg))
+    for s in range(n_seg):
+        n = int(n_cells[s])
+        c0, i0, j = int(cell_off[s]), int(cell_off[s]) + s, n // 2
+        left, right = (rl[s], ul[s], pl[s]), (rr[s], ur[s], pr[s])
+        for v in range(3):
+            W[v, c0:c0 + j] = left[v]
+            W[v, c0 + j:c0 + n] = right[v]
+            WL[v, i0:i0 + j + 1] = left[v]      # interfaces 0..j: left limit is the left state
+            WL[v, i0 + j + 1:i0 + n + 1] = right[v]
+            WR[v, i0:i0 + j] = left[v]          # interfaces 0..j-1: right limit is the left state
+            WR[v, i0 + j:i0 + n + 1] = right[v]
+    q = prim_to_cons(W[0], W[1], W[2], gamma)
+    vl = prim_to_cons(WL[0], WL[1], WL[2], gamma)
+    vr = prim_to_cons(WR[0], WR[1], WR[2], gamma)
+    return Network(n_cells, lengths, np.zeros(n_seg), cell_off, dx, q, vl, vr)

@@ -188,3 +188,41 @@ def test_nl_parameter_validation(G):
         kw.update(bad)
         with pytest.raises(G.GrprecError):
             G.Simulation(G.GRPREC_ADVECTION, 3, [64], [1.0], q, vl, vr, **kw)
+
+
+@pytest.mark.parametrize("guess", [0, 1])
+def test_tube_network_parity(G, guess):
+    """Batched shock tubes (the seeded tube network's first 80 tubes), GRPrecNL
+    order 3, with the PVRS or the learned Newton start (random network weights,
+    gate 0.1, so it is taken at the jumps): every tube after 12 of its own
+    steps equals the single-domain oracle."""
+    full = I.tube_network(n_seg=80)
+    S = len(full.n_cells)
+    c = _ocfg(oracle.EULER, 3, oracle.TRANSMISSIVE, 10.0)
+    v0 = oracle.init_interfaces(c, full.vl, full.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, full.cell_off, full.dx, full.q, v0, np.zeros(S), 1e9, 12)
+    kw = {}
+    if guess:
+        rng = np.random.default_rng(5)
+        P = rng.normal(scale=0.3, size=1325)
+        P[1313:1319] = rng.normal(scale=0.1, size=6)
+        P[1319:1325] = rng.uniform(0.5, 2.0, size=6)
+        kw = dict(guess=G.GRPREC_GUESS_MLP, mlp_params=torch.from_numpy(P.astype(np.float32)).cuda())
+    sim = _sim(G, G.GRPREC_EULER, 3, full.n_cells, full.lengths, full.q, full.vl, full.vr,
+               G.GRPREC_BC_TRANSMISSIVE, 10.0, schedule=G.GRPREC_SCHED_FLAT_TILES, block=64, **kw)
+    try:
+        print(f"tube network guess {guess}", flush=True)
+        G.grprec_enable_stats(sim.h, True)
+        steps, _ = sim.run(1e9, 12)
+        st = G.grprec_get_stats(sim.h)
+        assert steps == 12
+        qg, vg, _, _ = sim.numpy_state()
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-14)
+    finally:
+        sim.close()
+    if guess:
+        assert st["mlp_guesses"] > 0
+    for s in range(S):
+        c0, c1 = full.cell_off[s], full.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
