@@ -307,17 +307,17 @@ __device__ __forceinline__ float mlp_tanh(float x) {
   return 1.0f - 2.0f / (e + 1.0f);
 }
 
-__device__ __forceinline__ void mlp_features(const Gas &G, const Prim &L, const Prim &R, float x[6],
-                                             double &pbar) {
-  double rbar = 0.5 * (L.r + R.r);
-  pbar = 0.5 * (L.p + R.p);
-  double cbar = sqrt(G.g * pbar / rbar);
-  x[0] = (float)log(L.r / rbar);
-  x[1] = (float)log(R.r / rbar);
-  x[2] = (float)log(L.p / pbar);
-  x[3] = (float)log(R.p / pbar);
-  x[4] = (float)(L.u / cbar);
-  x[5] = (float)(R.u / cbar);
+__device__ __forceinline__ void mlp_features(double g, double rl, double ul, double pl, double rr,
+                                             double ur, double pr, float x[6], double &pbar) {
+  double rbar = 0.5 * (rl + rr);
+  pbar = 0.5 * (pl + pr);
+  double cbar = sqrt(g * pbar / rbar);
+  x[0] = (float)log(rl / rbar);
+  x[1] = (float)log(rr / rbar);
+  x[2] = (float)log(pl / pbar);
+  x[3] = (float)log(pr / pbar);
+  x[4] = (float)(ul / cbar);
+  x[5] = (float)(ur / cbar);
 }
 
 __device__ __forceinline__ float mlp_eval(const float *__restrict__ P, const float xin[6]) {
@@ -356,11 +356,13 @@ __device__ __forceinline__ bool jump_exceeds(const Prim &L, const Prim &R, doubl
 
 // The network's star-pressure proposal, or 0 when it is not positive and
 // finite.  Kept out of line: it is large and, behind the gate, rarely taken.
-__device__ __noinline__ double learned_pressure(const Gas &G, const Prim &L, const Prim &R,
-                                                const float *mlp) {
+// Arguments travel by value: a reference to a local would put that local in
+// private memory on every path, taken or not.
+__device__ __noinline__ double learned_pressure(double g, double rl, double ul, double pl, double rr,
+                                                double ur, double pr, const float *mlp) {
   float x[6];
   double pb;
-  mlp_features(G, L, R, x, pb);
+  mlp_features(g, rl, ul, pl, rr, ur, pr, x, pb);
   const float y = mlp_eval(mlp, x);
   const double p0 = pb * exp((double)y);
   return (p0 > 0.0 && isfinite(p0)) ? p0 : 0.0;
@@ -372,7 +374,7 @@ __device__ __forceinline__ double start_pressure(const Gas &G, const Prim &L, co
                                                  double gate, const float *mlp, bool &used_mlp) {
   used_mlp = false;
   if (guess == 1 && mlp != nullptr && jump_exceeds(L, R, gate)) {
-    const double p0 = learned_pressure(G, L, R, mlp);
+    const double p0 = learned_pressure(G.g, L.r, L.u, L.p, R.r, R.u, R.p, mlp);
     if (p0 > 0.0) {
       used_mlp = true;
       return p0;
@@ -389,22 +391,25 @@ struct RSOut {
   double Q[3];
   double pstar;
   int iters;
+  bool strong;  // the data jump passed the gate (when it was tested)
+  bool learned; // Newton started from the learned proposal
 };
 
 // Start of the Newton iteration: pguess when positive, else PVRS.  With
-// strong != nullptr the data jump is first tested against the gate and the
-// result stored there; below the gate Newton starts from PVRS (already
-// accurate to second order in the jump for weak waves), above it from the
-// learned proposal when mlp != nullptr (`used` reports that), else from
-// pguess when positive.
+// test_gate the data jump is first tested against the gate (o.strong); below
+// the gate Newton starts from PVRS (already accurate to second order in the
+// jump for weak waves), above it from the learned proposal when
+// mlp != nullptr (o.learned), else from pguess when positive.
 __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], const double QR[3],
                                              double pguess, int maxit, double tol, RSOut &o,
                                              const float *mlp = nullptr, double gate = 0.0,
-                                             bool *used = nullptr, bool *strong = nullptr) {
+                                             bool test_gate = false) {
   Prim L, R;
   bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
   bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
   o.iters = 0;
+  o.strong = false;
+  o.learned = false;
   if (!(okl && okr)) {
     o.F[0] = o.F[1] = o.F[2] = 0.0;
     o.Q[0] = QL[0]; o.Q[1] = QL[1]; o.Q[2] = QL[2];
@@ -418,12 +423,12 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
     return ERR_VACUUM;
   }
   double p0 = 0.0;
-  if (strong != nullptr) {
-    *strong = jump_exceeds(L, R, gate);
-    if (*strong && mlp != nullptr) {
-      p0 = learned_pressure(G, L, R, mlp);
-      if (p0 > 0.0) *used = true;
-    } else if (*strong) {
+  if (test_gate) {
+    o.strong = jump_exceeds(L, R, gate);
+    if (o.strong && mlp != nullptr) {
+      p0 = learned_pressure(G.g, L.r, L.u, L.p, R.r, R.u, R.p, mlp);
+      o.learned = p0 > 0.0;
+    } else if (o.strong) {
       p0 = pguess;
     }
   } else {

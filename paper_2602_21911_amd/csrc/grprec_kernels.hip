@@ -343,11 +343,11 @@ void euler_step(EulerArgs<M> a) {
         // from the previous time's star pressure, below it (and without
         // either option) every time starts from PVRS
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
-        bool used = false;
         RSOut o;
         err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
-                        a.gate, &used, (b == 0 && gated) ? &strong : nullptr);
-        st_mlp += used ? 1 : 0;
+                        a.gate, b == 0 && gated);
+        if (b == 0) strong = o.strong;
+        st_mlp += o.learned ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
@@ -390,11 +390,11 @@ void euler_step(EulerArgs<M> a) {
       for (int b = 0; b < NT; ++b) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
-        bool used = false;
         RSOut o;
         err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
-                        a.gate, &used, (b == 0 && gated) ? &strong : nullptr);
-        st_mlp += used ? 1 : 0;
+                        a.gate, b == 0 && gated);
+        if (b == 0) strong = o.strong;
+        st_mlp += o.learned ? 1 : 0;
         pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;

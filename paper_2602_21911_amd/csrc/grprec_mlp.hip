@@ -65,7 +65,7 @@ __global__ void features_kernel(const double *wl, const double *wr, const double
     R.r = wr[3 * i]; R.u = wr[3 * i + 1]; R.p = wr[3 * i + 2];
     float f[6];
     double pbar;
-    mlp_features(G, L, R, f, pbar);
+    mlp_features(G.g, L.r, L.u, L.p, R.r, R.u, R.p, f, pbar);
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[6 * i + k] = f[k];
     if (pstar && y) y[i] = (float)log(pstar[i] / pbar);
