@@ -22,6 +22,7 @@ OK, E_INVALID, E_NONPHYSICAL, E_VACUUM, E_NEWTON, E_PREDICTOR = 0, -1, -4, -5, -
 ADVECTION, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LINEAR, NONLINEAR = 0, 1          # GRPrec (Sec. 3.1) or GRPrecNL (Sec. 3.3-3.4)
+DATUM_EXACT, DATUM_TRRS = 0, 1    # Euler interface datum solver (Sec. 4.1)
 
 
 def build(force: bool = True) -> str:
@@ -41,7 +42,7 @@ class Cfg(ctypes.Structure):
                 ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int),
                 ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
                 ("recon", ctypes.c_int), ("nl_lambda_c", ctypes.c_double),
-                ("nl_eps", ctypes.c_double), ("nl_r", ctypes.c_double)]
+                ("nl_eps", ctypes.c_double), ("nl_r", ctypes.c_double), ("datum", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -79,6 +80,7 @@ def lib():
         L.orc_run_segment.argtypes = [ctypes.POINTER(Cfg), ctypes.c_int, ctypes.c_double, _D, _D,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _I64,
                                       ctypes.POINTER(Stats)]
+        L.orc_trrs.argtypes = [ctypes.c_double, _D, _D, _D, _D, _D]
         L.orc_side_matrix.argtypes = [ctypes.c_int, ctypes.c_int, _D]
         L.orc_oi.argtypes = [ctypes.c_int, _D, ctypes.c_double]
         L.orc_oi.restype = ctypes.c_double
@@ -97,13 +99,13 @@ def _p(a: np.ndarray):
 
 def cfg(system=ADVECTION, order=3, cfl=0.9, lam=1.0, gamma=1.4, bc=PERIODIC, newton_tol=1e-12,
         newton_max=50, picard_tol=1e-13, picard_max=64, recon=LINEAR, nl_lambda_c=10.0,
-        nl_eps=1e-14, nl_r=4.0) -> Cfg:
+        nl_eps=1e-14, nl_r=4.0, datum=DATUM_EXACT) -> Cfg:
     """GRPrecNL weights: r and eps as printed (Sec. 3.3).  lambda_C defaults to
     10, the value under which the scheme reproduces the paper's GRPrecNL
     results (Sec. 4.2.3 table, Sec. 4.2.2 square wave); the printed 1e9 makes
     GRPrecNL coincide with GRPrec on smooth data (pass nl_lambda_c=1e9)."""
     return Cfg(system, order - 1, cfl, lam, gamma, bc, bc, newton_tol, newton_max, picard_tol,
-               picard_max, recon, nl_lambda_c, nl_eps, nl_r)
+               picard_max, recon, nl_lambda_c, nl_eps, nl_r, datum)
 
 
 class OracleError(RuntimeError):
@@ -213,6 +215,15 @@ def riemann_rc(gamma, WL, WR, guess=-1.0, tol=1e-12, maxit=50):
     rc = lib().orc_riemann(gamma, _p(WL), _p(WR), guess, tol, maxit, ctypes.byref(ps),
                            ctypes.byref(us), _p(W0), ctypes.byref(it))
     return rc, ps.value, it.value
+
+
+def trrs(gamma, WL, WR):
+    """Two-rarefaction solver: (p*, u*, primitive state at x/t = 0)."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    ps, us, W0 = np.zeros(1), np.zeros(1), np.zeros(3)
+    _chk(lib().orc_trrs(gamma, _p(WL), _p(WR), _p(ps), _p(us), _p(W0)), "trrs")
+    return ps[0], us[0], W0
 
 
 def pvrs_guess(gamma, WL, WR):

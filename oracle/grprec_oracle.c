@@ -20,7 +20,9 @@
  *     predictor iterated to a fixed point, then classical Riemann problems at
  *     the time integration points of the flux integral (eq. numfluxes);
  *   - the interface datum for the next reconstruction is the Riemann solution at
- *     the interface at the end of the step, q_{i+1/2}(dt) (Sec. 3.1);
+ *     the interface at the end of the step, q_{i+1/2}(dt) (Sec. 3.1), from the
+ *     exact solver or, for the Euler equations, optionally from the
+ *     two-rarefaction approximation (Sec. 4.1);
  *   - time step from eq. (dt-FV) with S_max as in Sec. 4.1;
  *   - conservative one-step update, eq. (eq_finite_volume), without source.
  * The paper gives no details of the DET predictor, of the exact Euler Riemann
@@ -57,6 +59,7 @@ typedef struct {
   double nl_lambda_c; /* GRPrecNL linear weight of the centred polynomial (1e9) */
   double nl_eps;      /* GRPrecNL epsilon (1e-14) */
   double nl_r;        /* GRPrecNL exponent r (4) */
+  int datum;          /* Euler interface datum: 0 = exact Riemann solver, 1 = two-rarefaction */
 } orc_cfg;
 
 typedef struct {
@@ -586,6 +589,68 @@ int orc_riemann(double g, const double *WL, const double *WR, double guess, doub
   return ORC_OK;
 }
 
+/* Two-rarefaction approximation of the Riemann problem, the solver Sec. 4.1
+ * names for the Euler interface datum.  Both nonlinear waves are taken as
+ * rarefactions, so across each the generalised Riemann invariant and the
+ * isentrope hold (p_s, u_s: star pressure and velocity; c_sK star sound speeds):
+ *   u_s + 2 c_sL/(g-1) = u_L + 2 c_L/(g-1),   c_sL = c_L (p_s / p_L)^z,
+ *   u_s - 2 c_sR/(g-1) = u_R - 2 c_R/(g-1),   c_sR = c_R (p_s / p_R)^z,
+ * z = (g-1)/(2 g).  Eliminating u_s gives
+ *   p_s^z (c_L p_L^-z + c_R p_R^-z) = c_L + c_R - (g-1)/2 (u_R - u_L),
+ * and u_s is the mean of the two invariant relations.  A non-positive
+ * right-hand side means vacuum.  The solution at x/t = 0 is sampled from the
+ * two-rarefaction pattern (left side when u_s >= 0). */
+int orc_trrs(double g, const double *WL, const double *WR, double *pstar, double *ustar, double *W0) {
+  double rl = WL[0], ul = WL[1], pl = WL[2];
+  double rr = WR[0], ur = WR[1], pr = WR[2];
+  if (!(rl > 0.0) || !(rr > 0.0) || !(pl > 0.0) || !(pr > 0.0)) return ORC_E_NONPHYSICAL;
+  if (!isfinite(ul) || !isfinite(ur)) return ORC_E_NONPHYSICAL;
+  double gm1 = g - 1.0, gp1 = g + 1.0, z = gm1 / (2.0 * g);
+  double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  double num = cl + cr - 0.5 * gm1 * (ur - ul);
+  if (!(num > 0.0)) return ORC_E_VACUUM;
+  double p = pow(num / (cl * pow(pl, -z) + cr * pow(pr, -z)), 1.0 / z);
+  double csl = cl * pow(p / pl, z), csr = cr * pow(p / pr, z);
+  double u = 0.5 * (ul + ur) + ((csr - cr) - (csl - cl)) / gm1;
+  *pstar = p;
+  *ustar = u;
+  if (u >= 0.0) {
+    if (ul - cl >= 0.0) {
+      W0[0] = rl; W0[1] = ul; W0[2] = pl;
+    } else if (u - csl < 0.0) {
+      W0[0] = rl * pow(p / pl, 1.0 / g); W0[1] = u; W0[2] = p;
+    } else {
+      double c = 2.0 / gp1 * (cl + 0.5 * gm1 * ul);
+      W0[0] = rl * pow(c / cl, 2.0 / gm1);
+      W0[1] = c;
+      W0[2] = pl * pow(c / cl, 2.0 * g / gm1);
+    }
+  } else {
+    if (ur + cr <= 0.0) {
+      W0[0] = rr; W0[1] = ur; W0[2] = pr;
+    } else if (u + csr >= 0.0) {
+      W0[0] = rr * pow(p / pr, 1.0 / g); W0[1] = u; W0[2] = p;
+    } else {
+      double c = 2.0 / gp1 * (cr - 0.5 * gm1 * ur);
+      W0[0] = rr * pow(c / cr, 2.0 / gm1);
+      W0[1] = -c;
+      W0[2] = pr * pow(c / cr, 2.0 * g / gm1);
+    }
+  }
+  return ORC_OK;
+}
+
+/* Interface datum by the two-rarefaction solver (conserved in and out). */
+static int orc_datum_trrs(const orc_cfg *cf, const double *QL, const double *QR, double *Q0) {
+  double WL[3], WR[3], W0[3], ps, us;
+  orc_cons_to_prim(cf->gamma, QL, WL);
+  orc_cons_to_prim(cf->gamma, QR, WR);
+  int rc = orc_trrs(cf->gamma, WL, WR, &ps, &us, W0);
+  if (rc != ORC_OK) return rc;
+  orc_prim_to_cons(cf->gamma, W0, Q0);
+  return ORC_OK;
+}
+
 /* Interface interaction on conserved traces: returns the physical flux of the
  * Riemann solution at x/t = 0 and that state (conserved). */
 static int orc_interact(const orc_cfg *cf, const double *QL, const double *QR, double *F, double *Q0,
@@ -818,6 +883,7 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
                      double t_end, double *q_out, double *v_out, double *dt_out, double *t_out,
                      orc_stats *st) {
   if (n < 1 || cf->m < 1 || cf->m > 4 || cf->recon < 0 || cf->recon > 1) return ORC_E_INVALID;
+  if (cf->datum < 0 || cf->datum > 1) return ORC_E_INVALID;
   int m = cf->m, nv = orc_nvar(cf), nn = m + 1;
   int per = (cf->bc_left == 0);
   double R[5 * 5];
@@ -924,7 +990,10 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
         QL[vv] = tl[vv * (nn + 1) + b];
         QR[vv] = tr[vv * (nn + 1) + b];
       }
-      rc = orc_interact(cf, QL, QR, F, Q0, st);
+      if (b == nn && cf->system == 1 && cf->datum == 1)
+        rc = orc_datum_trrs(cf, QL, QR, Q0); /* end-of-step datum only */
+      else
+        rc = orc_interact(cf, QL, QR, F, Q0, st);
       if (rc != ORC_OK) break;
       if (b < nn) {
         for (int vv = 0; vv < nv; ++vv) Fbar[vv] += s.w[b] * F[vv];
@@ -957,7 +1026,8 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
 
 /* Interface data at t = 0 (the paper does not say how the first step gets
  * them): the Riemann solution at x/t = 0 between the one-sided limits of the
- * initial condition at each interface (equal limits give the point value). */
+ * initial condition at each interface (equal limits give the point value),
+ * by the same solver that provides the datum in later steps. */
 int orc_init_interfaces(const orc_cfg *cf, int nif, const double *vl, const double *vr, double *v) {
   int nv = orc_nvar(cf);
   for (int k = 0; k < nif; ++k) {
@@ -966,7 +1036,8 @@ int orc_init_interfaces(const orc_cfg *cf, int nif, const double *vl, const doub
       QL[vv] = vl[vv * nif + k];
       QR[vv] = vr[vv * nif + k];
     }
-    int rc = orc_interact(cf, QL, QR, F, Q0, NULL);
+    int rc = (cf->system == 1 && cf->datum == 1) ? orc_datum_trrs(cf, QL, QR, Q0)
+                                                 : orc_interact(cf, QL, QR, F, Q0, NULL);
     if (rc != ORC_OK) return rc;
     for (int vv = 0; vv < nv; ++vv) v[vv * nif + k] = Q0[vv];
   }

@@ -138,3 +138,98 @@ def test_guess_independence(WL, WR):
     for guess in (1e-3 * ps0, 0.5 * ps0, 2 * ps0, 30 * ps0):
         ps, _, _, _ = oracle.riemann(G, WL, WR, guess=guess)
         assert abs(ps - ps0) < 1e-12 * ps0
+
+
+# ------------------------------------------------- two-rarefaction datum (Sec. 4.1)
+def _raref_f(g, p, r, u, pk):
+    """Rarefaction-branch pressure function of one side (isentrope + Riemann
+    invariant), written out directly."""
+    c = np.sqrt(g * pk / r)
+    return 2.0 * c / (g - 1.0) * ((p / pk) ** ((g - 1.0) / (2.0 * g)) - 1.0)
+
+
+def test_trrs_equals_exact_solver_for_two_rarefactions():
+    """When the exact solution has two rarefactions (p* below both pressures)
+    the approximation is exact: same p*, u* and state at x/t = 0."""
+    rng = np.random.default_rng(31)
+    seen = 0
+    cases = [((1.0, -2.0, 0.4), (1.0, 2.0, 0.4))]  # the paper's 123 problem data
+    for _ in range(400):
+        WL = (np.exp(rng.uniform(-1, 1)), rng.uniform(-1, 0), np.exp(rng.uniform(-1, 1)))
+        WR = (np.exp(rng.uniform(-1, 1)), rng.uniform(0, 1), np.exp(rng.uniform(-1, 1)))
+        cases.append((WL, WR))
+    for WL, WR in cases:
+        rc, pe, _ = oracle.riemann_rc(1.4, WL, WR)
+        if rc != oracle.OK or pe >= min(WL[2], WR[2]):
+            continue
+        seen += 1
+        ps, us, W0 = oracle.trrs(1.4, WL, WR)
+        pe, ue, We, _ = oracle.riemann(1.4, WL, WR)
+        assert abs(ps - pe) <= 1e-11 * pe and abs(us - ue) <= 1e-11 * (1 + abs(ue))
+        np.testing.assert_allclose(W0, We, rtol=1e-11, atol=1e-13)
+    assert seen > 100
+
+
+@pytest.mark.parametrize("g", [1.4, 5.0 / 3.0, 1.2])
+def test_trrs_solves_the_two_rarefaction_pressure_equation(g):
+    """p* is the root of f_L + f_R + u_R - u_L = 0 with both sides on the
+    rarefaction branch (also for data whose exact solution has shocks), and
+    u* = (u_L + u_R)/2 + (f_R - f_L)/2."""
+    rng = np.random.default_rng(32)
+    for _ in range(200):
+        WL = (np.exp(rng.uniform(-2, 2)), rng.uniform(-1, 1), np.exp(rng.uniform(-2, 2)))
+        WR = (np.exp(rng.uniform(-2, 2)), rng.uniform(-1, 1), np.exp(rng.uniform(-2, 2)))
+        try:
+            ps, us, _ = oracle.trrs(g, WL, WR)
+        except oracle.OracleError:
+            continue
+        fl = _raref_f(g, ps, WL[0], WL[1], WL[2])
+        fr = _raref_f(g, ps, WR[0], WR[1], WR[2])
+        scale = np.sqrt(g * WL[2] / WL[0]) + np.sqrt(g * WR[2] / WR[0])
+        assert abs(fl + fr + WR[1] - WL[1]) <= 1e-12 * scale
+        assert abs(us - (0.5 * (WL[1] + WR[1]) + 0.5 * (fr - fl))) <= 1e-12 * scale
+
+
+def test_trrs_mirror_symmetry_and_shock_bias():
+    """Mirrored data (swap sides, negate velocities) give the same p* and the
+    negated u*; where the exact solution has a shock, the rarefaction curve
+    lies below the Hugoniot curve, so the approximate p* is not below the
+    exact one (Sod: 0.3068 vs 0.3031)."""
+    rng = np.random.default_rng(33)
+    shocks = 0
+    for _ in range(300):
+        WL = (np.exp(rng.uniform(-2, 2)), rng.uniform(-1, 1), np.exp(rng.uniform(-2, 2)))
+        WR = (np.exp(rng.uniform(-2, 2)), rng.uniform(-1, 1), np.exp(rng.uniform(-2, 2)))
+        try:
+            ps, us, W0 = oracle.trrs(1.4, WL, WR)
+        except oracle.OracleError:
+            continue
+        pm, um, Wm = oracle.trrs(1.4, (WR[0], -WR[1], WR[2]), (WL[0], -WL[1], WL[2]))
+        assert abs(pm - ps) <= 1e-13 * ps and abs(um + us) <= 1e-13 * (1 + abs(us))
+        if abs(us) > 1e-12:
+            np.testing.assert_allclose(Wm, [W0[0], -W0[1], W0[2]], rtol=1e-12, atol=1e-14)
+        rc, pe, _ = oracle.riemann_rc(1.4, WL, WR)
+        if rc == oracle.OK and pe > min(WL[2], WR[2]):
+            shocks += 1
+            assert ps >= pe * (1 - 1e-12)
+    assert shocks > 50
+    ps, _, _ = oracle.trrs(1.4, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    pe, _, _, _ = oracle.riemann(1.4, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert ps > pe
+
+
+def test_trrs_weak_waves_and_vacuum():
+    """Weak jumps: the approximation differs from the exact solution at third
+    order in the jump (Hugoniot and isentrope agree to second order); vacuum
+    is reported by the same criterion as the exact solver."""
+    base = np.array([1.0, 0.2, 1.0])
+    errs = []
+    for eps in (1e-2, 5e-3):
+        WR = base * np.array([1 + eps, 1.0, 1 + 2 * eps])  # compression: a weak shock
+        ps, _, _ = oracle.trrs(1.4, base, WR)
+        pe, _, _, _ = oracle.riemann(1.4, base, WR)
+        errs.append(abs(ps - pe))
+    assert errs[1] < errs[0] / 6.0  # ~ eps^3: ratio 8
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.trrs(1.4, (1.0, -6.0, 0.4), (1.0, 6.0, 0.4))
+    assert ei.value.code == oracle.E_VACUUM
