@@ -175,12 +175,12 @@ def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0):
             "traffic": traffic}
 
 
-def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon):
+def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon, datum=0):
     """Rate of one batched form, and its solver counters over the same steps
     (counted in a second, untimed run)."""
     cells = int(net.n_cells.sum())
     kw = dict(bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params, schedule=schedule,
-              block=block, recon=recon)
+              block=block, recon=recon, datum=datum)
     sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr, **kw)
     try:
         sched, blk = G.grprec_get_schedule(sim.h)
@@ -218,16 +218,23 @@ def bench_tube_network(G, torch, params, steps=100, warmup=10):
     if params is not None:
         out["batched_pvrs"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, a["schedule"],
                                             a["block"], steps, warmup, 1)
+    out["batched_pvrs_trrs_datum"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None,
+                                                   a["schedule"], a["block"], steps, warmup, 1,
+                                                   G.GRPREC_DATUM_TRRS)
     return out
 
 
-def bench_network_nl(G, torch, steps=100, warmup=10):
-    """The headline network with GRPrecNL instead of GRPrec (PVRS start)."""
+def bench_network_variants(G, torch, steps=100, warmup=10):
+    """The headline network with GRPrecNL instead of GRPrec, and with the
+    two-rarefaction datum instead of the exact one (PVRS start)."""
     from paper_2602_21911_amd import inputs as I
     net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
-    r = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1)
-    r["cells"] = int(net.n_cells.sum())
-    return r
+    out = {"cells": int(net.n_cells.sum())}
+    out["grprecnl"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0,
+                                    steps, warmup, 1)
+    out["trrs_datum"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0,
+                                      steps, warmup, 0, G.GRPREC_DATUM_TRRS)
+    return out
 
 
 def bench_euler_single(G, torch, n, order=3, steps=50, warmup=5):
@@ -262,8 +269,9 @@ def cpu_baseline(net, steps: int):
 
 def counters_run(G, torch, I):
     """Short fixed workload for rocprofv3 --pmc passes: 3 network steps (flat
-    tiles, 64-wide blocks), 3 advection steps on 2^25 cells, and a 256 MiB
-    device copy used to calibrate the byte counters."""
+    tiles, 64-wide blocks), 3 advection steps on 2^25 cells for GRPrec order 3
+    and 5 and GRPrecNL order 3, and a 256 MiB device copy used to calibrate
+    the byte counters."""
     net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
     sim = make_network(G, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_FLAT_TILES, 64)
     try:
@@ -273,13 +281,15 @@ def counters_run(G, torch, I):
     finally:
         sim.close()
     dx, q, vl, vr = I.adv_sin2pi(1 << 25)
-    sim = G.Simulation(G.GRPREC_ADVECTION, 3, [1 << 25], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
-    try:
-        for _ in range(3):
-            sim.step(1e9)
-        torch.cuda.synchronize()
-    finally:
-        sim.close()
+    for order, recon in ((3, 0), (5, 0), (3, 1)):
+        sim = G.Simulation(G.GRPREC_ADVECTION, order, [1 << 25], [1.0], q, vl, vr,
+                           bc=G.GRPREC_BC_PERIODIC, recon=recon)
+        try:
+            for _ in range(3):
+                sim.step(1e9)
+            torch.cuda.synchronize()
+        finally:
+            sim.close()
     a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
@@ -387,7 +397,7 @@ def main():
                              bench_advection(G, torch, 1 << 25, recon=1),
                              bench_advection(G, torch, 1 << 25, order=5, recon=1)]
         line["euler_single_domain"] = bench_euler_single(G, torch, 1 << 22)
-        line["network_grprecnl"] = bench_network_nl(G, torch)
+        line["network_variants"] = bench_network_variants(G, torch)
         line["tube_network"] = bench_tube_network(G, torch, params)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)

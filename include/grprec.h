@@ -70,6 +70,12 @@ enum {
                               omega_k = lambda_k / (eps + OI_k)^4, lambda_L = lambda_R = 1;
                               for the Euler equations in characteristic variables */
 };
+/* Solver of the end-of-step interface datum (Euler). */
+enum {
+  GRPREC_DATUM_EXACT = 0, /* exact Riemann solver, as for the fluxes */
+  GRPREC_DATUM_TRRS = 1   /* two-rarefaction approximation (Sec. 4.1): closed form, no
+                             iteration; also used for the first-step data */
+};
 /* How cells are grouped into workgroup tiles (Euler). */
 enum {
   GRPREC_SCHED_AUTO = 0,          /* autotune at init over the others */
@@ -126,6 +132,7 @@ typedef struct {
                           GRPrecNL equals GRPrec on smooth data, while its GRPrecNL
                           results are reproduced with 10) */
   double nl_eps;       /* GRPrecNL epsilon, [1e-30, 1] (default 1e-14 when 0) */
+  int datum;           /* GRPREC_DATUM_* (Euler only) */
 } grprec_problem;
 
 typedef struct {

@@ -17,8 +17,8 @@ namespace grp {
 template <int M> hipError_t launch_euler(const EulerArgs<M> &, int, int, bool, hipStream_t);
 template <int M> hipError_t euler_occupancy(int, bool, int *);
 template <int M> hipError_t launch_adv(const AdvArgs<M> &, int, bool, hipStream_t);
-hipError_t launch_init_interfaces_euler(double *, const double *, int, const Gas &, int, double, Ctl *,
-                                        hipStream_t);
+hipError_t launch_init_interfaces_euler(double *v0, const double *v1, int ti, const Gas &G, int maxit,
+                                        double tol, int datum, Ctl *ctl, hipStream_t st);
 hipError_t launch_init_interfaces_adv(double *, const double *, int, double, hipStream_t);
 hipError_t launch_domain_smax(const double *, int, const Seg &, int, const Gas &, Ctl *, hipStream_t);
 hipError_t launch_reset_ctl(Ctl *, const Seg &, double, long long, int, double, hipStream_t);
@@ -242,6 +242,7 @@ static EulerArgs<M> euler_args(const grprec_handle *h, int slot) {
   a.hv = h->hv;
   a.nl_lambda_c = h->p.nl_lambda_c;
   a.nl_eps = h->p.nl_eps;
+  a.datum = h->p.datum;
   return a;
 }
 
@@ -419,6 +420,8 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   // bounds that keep the weights' products of fourth powers inside double range
   if (!(p.nl_lambda_c > 0.0 && p.nl_lambda_c <= 1e30)) return GRPREC_E_INVALID;
   if (!(p.nl_eps >= 1e-30 && p.nl_eps <= 1.0)) return GRPREC_E_INVALID;
+  if (p.datum != GRPREC_DATUM_EXACT && p.datum != GRPREC_DATUM_TRRS) return GRPREC_E_INVALID;
+  if (p.datum == GRPREC_DATUM_TRRS && p.system != GRPREC_EULER) return GRPREC_E_INVALID;
   if (p.guess == GRPREC_GUESS_MLP && !p.mlp_params) return GRPREC_E_INVALID;
   if (p.block != 0 && p.block != 64 && p.block != 128 && p.block != 256) return GRPREC_E_INVALID;
   if (p.schedule < GRPREC_SCHED_AUTO || p.schedule > GRPREC_SCHED_PER_DOMAIN) return GRPREC_E_INVALID;
@@ -482,7 +485,8 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (launch_reset_ctl(h->ctl, h->seg, 0.0, 0, 0, smax_const, h->stream) != hipSuccess) return fail(GRPREC_E_HIP);
   hipError_t e;
   if (p.system == GRPREC_EULER) {
-    e = launch_init_interfaces_euler(h->v0, h->v1, (int)h->ti, h->gas, p.max_newton, p.newton_tol, h->ctl,
+    e = launch_init_interfaces_euler(h->v0, h->v1, (int)h->ti, h->gas, p.max_newton, p.newton_tol, p.datum,
+                                     h->ctl,
                                      h->stream);
     if (e == hipSuccess) e = launch_domain_smax(h->q0, (int)h->tc, h->seg, 0, h->gas, h->ctl, h->stream);
   } else {

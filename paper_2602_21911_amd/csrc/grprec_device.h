@@ -452,6 +452,72 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
   return it > maxit ? ERR_NEWTON : 0u;
 }
 
+// ---------------------------------------------------------------- two-rarefaction datum
+// Two-rarefaction approximation of the Riemann problem (the solver Sec. 4.1
+// names for the Euler interface datum): with both nonlinear waves taken as
+// rarefactions the Riemann invariants and isentropes give
+//   X = p_s^z = (c_L + c_R - (g-1)/2 (u_R - u_L)) / (c_L p_L^-z + c_R p_R^-z),
+//   c_sK = c_K X / p_K^z,  u_s = (u_L + u_R)/2 + ((c_sR - c_R) - (c_sL - c_L))/(g-1),
+// no iteration.  The state at x/t = 0 is sampled from the two-rarefaction
+// pattern (left side when u_s >= 0); o.Q, o.F and o.pstar as interact().
+__device__ __forceinline__ unsigned trrs_interact(const Gas &G, const double QL[3], const double QR[3],
+                                                  RSOut &o) {
+  Prim L, R;
+  const bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
+  const bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
+  o.iters = 0;
+  o.strong = false;
+  o.learned = false;
+  const double num = L.c + R.c - 0.5 * G.gm1 * (R.u - L.u);
+  if (!(okl && okr) || !(num > 0.0)) {
+    o.F[0] = o.F[1] = o.F[2] = 0.0;
+    o.Q[0] = QL[0]; o.Q[1] = QL[1]; o.Q[2] = QL[2];
+    o.pstar = 0.0;
+    return (okl && okr) ? ERR_VACUUM : ERR_NONPHYS;
+  }
+  const double izl = rcp(pow_z(G, L.p)), izr = rcp(pow_z(G, R.p));  // p_K^-z
+  const double X = num * rcp(L.c * izl + R.c * izr);
+  const double ps = G.root_n > 0 ? ipow(X, G.root_n) : powpos(X, 1.0 / G.z);
+  const double wl = X * izl, wr = X * izr;  // (p_s / p_K)^z
+  const double csl = L.c * wl, csr = R.c * wr;
+  const double us = 0.5 * (L.u + R.u) + ((csr - R.c) - (csl - L.c)) * G.inv_gm1;
+  double r, u, p;
+  if (us >= 0.0) {
+    if (L.u - L.c >= 0.0) {
+      r = L.r; u = L.u; p = L.p;
+    } else if (us - csl < 0.0) {
+      r = L.r * dens_pow(G, wl); u = us; p = ps;
+    } else {  // fan: u - c = 0 and u + 2c/(g-1) is carried from the left
+      const double c = G.two_gp1 * (L.c + 0.5 * G.gm1 * L.u);
+      const double cr = c * L.ic;
+      r = L.r * powpos(cr, G.two_gm1);
+      u = c;
+      p = L.p * powpos(cr, G.twog_gm1);
+    }
+  } else {
+    if (R.u + R.c <= 0.0) {
+      r = R.r; u = R.u; p = R.p;
+    } else if (us + csr >= 0.0) {
+      r = R.r * dens_pow(G, wr); u = us; p = ps;
+    } else {  // fan: u + c = 0 and u - 2c/(g-1) is carried from the right
+      const double c = G.two_gp1 * (R.c - 0.5 * G.gm1 * R.u);
+      const double cr = c * R.ic;
+      r = R.r * powpos(cr, G.two_gm1);
+      u = -c;
+      p = R.p * powpos(cr, G.twog_gm1);
+    }
+  }
+  o.pstar = ps;
+  const double E = p * G.inv_gm1 + 0.5 * r * u * u;
+  o.Q[0] = r;
+  o.Q[1] = r * u;
+  o.Q[2] = E;
+  o.F[0] = r * u;
+  o.F[1] = r * u * u + p;
+  o.F[2] = u * (E + p);
+  return 0u;
+}
+
 // ---------------------------------------------------------------- GRPrecNL
 // Nonlinear combination of the left, centred and right candidates for one
 // scalar field (Sec. 3.3).  aC: the centred (GRPrec) coefficients; del[k]:

@@ -116,6 +116,7 @@ struct EulerArgs {
   const float *mlp;
   Harvest hv;
   double nl_lambda_c, nl_eps;  // GRPrecNL weights (used by the NL instantiations)
+  int datum;                   // end-of-step datum: 0 exact Riemann solver, 1 two-rarefaction
 };
 
 template <int M>

@@ -344,8 +344,11 @@ void euler_step(EulerArgs<M> a) {
         // either option) every time starts from PVRS
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         RSOut o;
-        err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
-                        a.gate, b == 0 && gated);
+        if (b == N && a.datum == 1)  // end-of-step datum by the two-rarefaction solver
+          err |= trrs_interact(G, QL, QR, o);
+        else
+          err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
+                          mlp, a.gate, b == 0 && gated);
         if (b == 0) strong = o.strong;
         st_mlp += o.learned ? 1 : 0;
         pw = o.pstar;
@@ -391,8 +394,11 @@ void euler_step(EulerArgs<M> a) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         RSOut o;
-        err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o, mlp,
-                        a.gate, b == 0 && gated);
+        if (b == N && a.datum == 1)  // end-of-step datum by the two-rarefaction solver
+          err |= trrs_interact(G, q0, QR, o);
+        else
+          err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
+                          mlp, a.gate, b == 0 && gated);
         if (b == 0) strong = o.strong;
         st_mlp += o.learned ? 1 : 0;
         pw = o.pstar;
@@ -705,13 +711,13 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
 // First-step interface data: the Riemann solution at x/t = 0 between the left
 // (v0) and right (v1) limits of the initial condition; written into v0.
 __global__ void init_interfaces_euler(double *v0, const double *v1, int ti, Gas G, int maxit,
-                                      double tol, Ctl *ctl) {
+                                      double tol, int datum, Ctl *ctl) {
   unsigned err = 0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ti; k += gridDim.x * blockDim.x) {
     double QL[3] = {v0[k], v0[ti + k], v0[2 * ti + k]};
     double QR[3] = {v1[k], v1[ti + k], v1[2 * ti + k]};
     RSOut o;
-    err |= interact(G, QL, QR, 0.0, maxit, tol, o);
+    err |= datum == 1 ? trrs_interact(G, QL, QR, o) : interact(G, QL, QR, 0.0, maxit, tol, o);
     v0[k] = o.Q[0];
     v0[ti + k] = o.Q[1];
     v0[2 * ti + k] = o.Q[2];
@@ -876,11 +882,12 @@ template hipError_t launch_adv<3>(const AdvArgs<3> &, int, bool, hipStream_t);
 template hipError_t launch_adv<4>(const AdvArgs<4> &, int, bool, hipStream_t);
 
 hipError_t launch_init_interfaces_euler(double *v0, const double *v1, int ti, const Gas &G, int maxit,
-                                        double tol, Ctl *ctl, hipStream_t st) {
+                                        double tol, int datum, Ctl *ctl, hipStream_t st) {
   int grid = (ti + 255) / 256;
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(init_interfaces_euler, dim3(grid), dim3(256), 0, st, v0, v1, ti, G, maxit, tol, ctl);
+  hipLaunchKernelGGL(init_interfaces_euler, dim3(grid), dim3(256), 0, st, v0, v1, ti, G, maxit, tol, datum,
+                     ctl);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ GRPREC_GUESS_PVRS, GRPREC_GUESS_MLP = 0, 1
 GRPREC_SCHED_AUTO, GRPREC_SCHED_SEGMENT_TILES, GRPREC_SCHED_FLAT_TILES, GRPREC_SCHED_PACKED = 0, 1, 2, 3
 GRPREC_SCHED_PER_DOMAIN = 4
 GRPREC_RECON_LINEAR, GRPREC_RECON_NL = 0, 1
+GRPREC_DATUM_EXACT, GRPREC_DATUM_TRRS = 0, 1
 GRPREC_MLP_WEIGHTS = 1313
 GRPREC_MLP_NPARAMS = 1325
 
@@ -58,7 +59,7 @@ class grprec_problem(ctypes.Structure):
                 ("picard_tol", ctypes.c_double), ("mlp_params", _vp),
                 ("mlp_gate", ctypes.c_double), ("warm_start", ctypes.c_int),
                 ("schedule", ctypes.c_int), ("block", ctypes.c_int), ("recon", ctypes.c_int),
-                ("nl_lambda_c", ctypes.c_double), ("nl_eps", ctypes.c_double)]
+                ("nl_lambda_c", ctypes.c_double), ("nl_eps", ctypes.c_double), ("datum", ctypes.c_int)]
 
 
 class grprec_buffers(ctypes.Structure):
@@ -296,7 +297,8 @@ class Simulation:
                  mlp_gate: float = 0.1, warm_start: int = 0, schedule: int = GRPREC_SCHED_AUTO,
                  block: int = 0, max_newton: int = 50, newton_tol: float = 1e-12,
                  max_picard: int = 64, picard_tol: float = 1e-13, recon: int = GRPREC_RECON_LINEAR,
-                 nl_lambda_c: float = 10.0, nl_eps: float = 1e-14, device: str = "cuda"):
+                 nl_lambda_c: float = 10.0, nl_eps: float = 1e-14, datum: int = GRPREC_DATUM_EXACT,
+                 device: str = "cuda"):
         import torch
         self.torch = torch
         self.cells = np.ascontiguousarray(cells, dtype=np.int64)
@@ -311,7 +313,7 @@ class Simulation:
                                 self.cells.ctypes.data_as(_i64p), self.lengths.ctypes.data_as(_dp),
                                 guess, max_newton, newton_tol, max_picard, picard_tol,
                                 None if mlp_params is None else mlp_params.data_ptr(), mlp_gate,
-                                warm_start, schedule, block, recon, nl_lambda_c, nl_eps)
+                                warm_start, schedule, block, recon, nl_lambda_c, nl_eps, datum)
         self.mlp_params = mlp_params
         wb = grprec_workspace_bytes(self.p)
         if wb == 0:
