@@ -48,7 +48,7 @@ extern "C" {
 
 #define GRPREC_OK 0
 #define GRPREC_E_INVALID (-1)     /* bad argument: order, CFL, sizes, pointers */
-#define GRPREC_E_UNSUPPORTED (-2) /* valid but not built, e.g. Euler order 5 */
+#define GRPREC_E_UNSUPPORTED (-2) /* valid but not built, e.g. advection with several domains */
 #define GRPREC_E_HIP (-3)         /* a HIP runtime call failed */
 #define GRPREC_E_NONPHYSICAL (-4) /* rho <= 0, p <= 0 or non-finite value */
 #define GRPREC_E_VACUUM (-5)      /* Riemann data generate vacuum */
@@ -103,7 +103,7 @@ typedef struct grprec_handle grprec_handle;
 
 typedef struct {
   int system;          /* GRPREC_ADVECTION or GRPREC_EULER */
-  int order;           /* m + 1: advection 2..5, Euler 2..4 */
+  int order;           /* m + 1: 2..5 */
   double cfl;          /* C_CFL of eq. (dt-FV), 0 < cfl <= 1 */
   double lambda;       /* advection speed, nonzero */
   double gamma;        /* ratio of specific heats, > 1 */

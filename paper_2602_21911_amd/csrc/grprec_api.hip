@@ -192,7 +192,8 @@ static int euler_occ(int M, int block, bool nl, int *occ) {
   switch (M) {
     case 1: e = euler_occupancy<1>(block, nl, occ); break;
     case 2: e = euler_occupancy<2>(block, nl, occ); break;
-    default: e = euler_occupancy<3>(block, nl, occ); break;
+    case 3: e = euler_occupancy<3>(block, nl, occ); break;
+    default: e = euler_occupancy<4>(block, nl, occ); break;
   }
   return hip_fail(e);
 }
@@ -280,7 +281,8 @@ static hipError_t launch_step(grprec_handle *h, int slot, hipStream_t st) {
     switch (h->M) {
       case 1: return launch_per_domain<1>(h, slot, st);
       case 2: return launch_per_domain<2>(h, slot, st);
-      default: return launch_per_domain<3>(h, slot, st);
+      case 3: return launch_per_domain<3>(h, slot, st);
+      default: return launch_per_domain<4>(h, slot, st);
     }
   }
   const bool nl = h->p.recon == GRPREC_RECON_NL;
@@ -288,7 +290,8 @@ static hipError_t launch_step(grprec_handle *h, int slot, hipStream_t st) {
     switch (h->M) {
       case 1: return launch_euler<1>(euler_args<1>(h, slot), h->block, h->grid, nl, st);
       case 2: return launch_euler<2>(euler_args<2>(h, slot), h->block, h->grid, nl, st);
-      default: return launch_euler<3>(euler_args<3>(h, slot), h->block, h->grid, nl, st);
+      case 3: return launch_euler<3>(euler_args<3>(h, slot), h->block, h->grid, nl, st);
+      default: return launch_euler<4>(euler_args<4>(h, slot), h->block, h->grid, nl, st);
     }
   }
   long long g = (h->tc + 255) / 256;
@@ -407,7 +410,6 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (!problem_ok(pin, &tc) || !b) return GRPREC_E_INVALID;
   if (!b->q0 || !b->q1 || !b->v0 || !b->v1 || !b->work) return GRPREC_E_INVALID;
   grprec_problem p = *pin;
-  if (p.system == GRPREC_EULER && p.order > 4) return GRPREC_E_UNSUPPORTED;
   if (p.system == GRPREC_ADVECTION && p.n_segments != 1) return GRPREC_E_UNSUPPORTED;
   if (p.max_newton <= 0) p.max_newton = 50;
   if (!(p.newton_tol > 0.0)) p.newton_tol = 1e-12;

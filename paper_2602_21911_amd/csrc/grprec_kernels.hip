@@ -79,7 +79,9 @@ __device__ __forceinline__ double pick(const double (&t)[N], int b) {
 
 // AIR: gamma is 1.4 and the gas constants are compile-time values.
 // NL: GRPrecNL reconstruction (Sec. 3.3-3.4) instead of GRPrec (Sec. 3.1).
-template <int M, int B, bool AIR, bool NL>
+// TR: end-of-step datum by the two-rarefaction solver (Sec. 4.1); a run-time
+// branch in the Riemann loop would cost registers on every path.
+template <int M, int B, bool AIR, bool NL, bool TR>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES)))
 void euler_step(EulerArgs<M> a) {
   constexpr int N = M + 1;   // nodes per direction
@@ -174,6 +176,7 @@ void euler_step(EulerArgs<M> a) {
         double Lm[3][3], Rm[3][3];
         euler_eigen(G, q0, Lm, Rm);
         double dm[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0}, dl[3], dr[3];
+        double dll[3] = {0.0, 0.0, 0.0}, drr[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
           if constexpr (M >= 2) {
@@ -182,6 +185,24 @@ void euler_step(EulerArgs<M> a) {
           }
           dl[v] = vin[v * ti + io + i] - q0[v];
           dr[v] = vin[v * ti + io + i + 1] - q0[v];
+          if constexpr (M == 4) {
+            // V_{i-3/2} and V_{i+3/2}: wrapped when periodic; beyond a
+            // transmissive end they belong to the ghost cell, a constant
+            // state equal to the end average
+            int kl = i - 1, kr = i + 2;
+            double vll, vrr;
+            if (a.periodic) {
+              if (kl < 0) kl += n;
+              if (kr > n) kr -= n;
+              vll = vin[v * ti + io + kl];
+              vrr = vin[v * ti + io + kr];
+            } else {
+              vll = kl >= 0 ? vin[v * ti + io + kl] : qin[v * tc + off];
+              vrr = kr <= n ? vin[v * ti + io + kr] : qin[v * tc + off + n - 1];
+            }
+            dll[v] = vll - q0[v];
+            drr[v] = vrr - q0[v];
+          }
         }
         double ac[3][M];
 #pragma unroll
@@ -193,6 +214,10 @@ void euler_step(EulerArgs<M> a) {
             del[2] = fma(Lm[f][v], dp[v], del[2]);
             del[3] = fma(Lm[f][v], dl[v], del[3]);
             del[4] = fma(Lm[f][v], dr[v], del[4]);
+            if constexpr (M == 4) {
+              del[5] = fma(Lm[f][v], dll[v], del[5]);
+              del[6] = fma(Lm[f][v], drr[v], del[6]);
+            }
           }
           double aC[M];
           grprec_from_diffs<M>(del[0], del[2], del[3], del[4], aC);
@@ -344,7 +369,7 @@ void euler_step(EulerArgs<M> a) {
         // either option) every time starts from PVRS
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         RSOut o;
-        if (b == N && a.datum == 1)  // end-of-step datum by the two-rarefaction solver
+        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
           err |= trrs_interact(G, QL, QR, o);
         else
           err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
@@ -394,7 +419,7 @@ void euler_step(EulerArgs<M> a) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
         const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         RSOut o;
-        if (b == N && a.datum == 1)  // end-of-step datum by the two-rarefaction solver
+        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
           err |= trrs_interact(G, q0, QR, o);
         else
           err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
@@ -819,10 +844,13 @@ __global__ void digest(const double *x, long long n, Ctl *ctl) {
 // (host-callable wrappers so that the API file needs no kernel templates)
 template <int M, int B, bool NL>
 static hipError_t launch_euler_mbn(const EulerArgs<M> &a, int grid, hipStream_t st) {
-  if (a.gas.g == kGammaAir)
-    hipLaunchKernelGGL((euler_step<M, B, true, NL>), dim3(grid), dim3(B), 0, st, a);
-  else
-    hipLaunchKernelGGL((euler_step<M, B, false, NL>), dim3(grid), dim3(B), 0, st, a);
+  if (a.gas.g == kGammaAir) {
+    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, true, NL, true>), dim3(grid), dim3(B), 0, st, a);
+    else hipLaunchKernelGGL((euler_step<M, B, true, NL, false>), dim3(grid), dim3(B), 0, st, a);
+  } else {
+    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, false, NL, true>), dim3(grid), dim3(B), 0, st, a);
+    else hipLaunchKernelGGL((euler_step<M, B, false, NL, false>), dim3(grid), dim3(B), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -843,8 +871,8 @@ hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, bool nl, hip
 
 template <int M, int B>
 static hipError_t euler_occ_b(bool nl, int *blocks_per_cu) {
-  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true>, B, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false>, B, 0);
+  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true, false>, B, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false, false>, B, 0);
 }
 
 template <int M>
@@ -873,9 +901,11 @@ hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
 template hipError_t launch_euler<1>(const EulerArgs<1> &, int, int, bool, hipStream_t);
 template hipError_t launch_euler<2>(const EulerArgs<2> &, int, int, bool, hipStream_t);
 template hipError_t launch_euler<3>(const EulerArgs<3> &, int, int, bool, hipStream_t);
+template hipError_t launch_euler<4>(const EulerArgs<4> &, int, int, bool, hipStream_t);
 template hipError_t euler_occupancy<1>(int, bool, int *);
 template hipError_t euler_occupancy<2>(int, bool, int *);
 template hipError_t euler_occupancy<3>(int, bool, int *);
+template hipError_t euler_occupancy<4>(int, bool, int *);
 template hipError_t launch_adv<1>(const AdvArgs<1> &, int, bool, hipStream_t);
 template hipError_t launch_adv<2>(const AdvArgs<2> &, int, bool, hipStream_t);
 template hipError_t launch_adv<3>(const AdvArgs<3> &, int, bool, hipStream_t);

@@ -67,7 +67,7 @@ def test_advection_nl_parity(G, order, kind, n, bc, lam_c):
         sim.close()
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("block", [64, 256])
 def test_euler_nl_density_wave_parity(G, order, block):
     n = 300
@@ -91,7 +91,7 @@ def test_euler_nl_density_wave_parity(G, order, block):
         sim.close()
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("lam_c", [10.0, 1e9])
 def test_euler_nl_acoustic_parity(G, order, lam_c):
     n = 200
@@ -111,7 +111,7 @@ def test_euler_nl_acoustic_parity(G, order, lam_c):
         sim.close()
 
 
-@pytest.mark.parametrize("order,ratio", [(2, 0.3), (3, 0.3), (4, 0.5)])
+@pytest.mark.parametrize("order,ratio", [(2, 0.3), (3, 0.3), (4, 0.5), (5, 0.5)])
 def test_euler_nl_shock_tube_parity(G, order, ratio):
     """Shock tubes that GRPrecNL carries to t = 0.2 (density and pressure
     ratio 0.3 at orders 2-3, 0.5 at order 4): jumps make the weights switch
@@ -190,15 +190,16 @@ def test_nl_parameter_validation(G):
             G.Simulation(G.GRPREC_ADVECTION, 3, [64], [1.0], q, vl, vr, **kw)
 
 
-@pytest.mark.parametrize("guess", [0, 1])
-def test_tube_network_parity(G, guess):
-    """Batched shock tubes (the seeded tube network's first 80 tubes), GRPrecNL
-    order 3, with the PVRS or the learned Newton start (random network weights,
-    gate 0.1, so it is taken at the jumps): every tube after 12 of its own
-    steps equals the single-domain oracle."""
-    full = I.tube_network(n_seg=80)
+@pytest.mark.parametrize("guess,order", [(0, 3), (1, 3), (0, 5)])
+def test_tube_network_parity(G, guess, order):
+    """Batched shock tubes (the seeded tube network's first 80 tubes; 40 at
+    order 5, whose degree-4 candidates read V_{i-3/2}, V_{i+3/2} and the ghost
+    states at the ends), GRPrecNL, with the PVRS or the learned Newton start
+    (random network weights, gate 0.1, so it is taken at the jumps): every tube
+    after 12 of its own steps equals the single-domain oracle."""
+    full = I.tube_network(n_seg=80 if order == 3 else 40)
     S = len(full.n_cells)
-    c = _ocfg(oracle.EULER, 3, oracle.TRANSMISSIVE, 10.0)
+    c = _ocfg(oracle.EULER, order, oracle.TRANSMISSIVE, 10.0)
     v0 = oracle.init_interfaces(c, full.vl, full.vr)
     qr, vr_, tr, _ = oracle.run_segments(c, full.cell_off, full.dx, full.q, v0, np.zeros(S), 1e9, 12)
     kw = {}
@@ -208,16 +209,18 @@ def test_tube_network_parity(G, guess):
         P[1313:1319] = rng.normal(scale=0.1, size=6)
         P[1319:1325] = rng.uniform(0.5, 2.0, size=6)
         kw = dict(guess=G.GRPREC_GUESS_MLP, mlp_params=torch.from_numpy(P.astype(np.float32)).cuda())
-    sim = _sim(G, G.GRPREC_EULER, 3, full.n_cells, full.lengths, full.q, full.vl, full.vr,
+    sim = _sim(G, G.GRPREC_EULER, order, full.n_cells, full.lengths, full.q, full.vl, full.vr,
                G.GRPREC_BC_TRANSMISSIVE, 10.0, schedule=G.GRPREC_SCHED_FLAT_TILES, block=64, **kw)
     try:
-        print(f"tube network guess {guess}", flush=True)
+        print(f"tube network guess {guess} order {order}", flush=True)
         G.grprec_enable_stats(sim.h, True)
         steps, _ = sim.run(1e9, 12)
         st = G.grprec_get_stats(sim.h)
         assert steps == 12
         qg, vg, _, _ = sim.numpy_state()
-        np.testing.assert_allclose(sim.times(), tr, rtol=1e-14)
+        # a time is a sum of C dx / S_max, and S_max carries the states'
+        # round-off differences (~1e-13 after a few steps across shocks)
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-12)
     finally:
         sim.close()
     if guess:

@@ -73,7 +73,7 @@ def test_advection_negative_speed_transmissive(G, order):
 
 
 # ------------------------------------------------------------- Euler
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("block", [64, 256])
 def test_euler_density_wave_parity(G, order, block):
     n = 300  # several tiles and a ragged tail at every block size
@@ -97,7 +97,7 @@ def test_euler_density_wave_parity(G, order, block):
         sim.close()
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_euler_acoustic_parity(G, order):
     """Genuinely nonlinear smooth flow (rho, u, p all vary)."""
     n = 130
@@ -238,3 +238,27 @@ def test_euler_weak_jumps_parity(G, order):
         assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
     finally:
         sim.close()
+
+
+@pytest.mark.parametrize("schedule,block", [(2, 64), (3, 128)])
+def test_network_parity_order5(G, schedule, block):
+    """Order 5 (degree 4) on the batched network: every segment after 3 of
+    its own steps equals the single-domain oracle."""
+    net = network_case(30, seed=6, nmax=300)
+    S = len(net.n_cells)
+    c = oracle_cfg(oracle.EULER, 5, oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 3)
+    sim = _gpu_sim(G, G.GRPREC_EULER, 5, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                   G.GRPREC_BC_TRANSMISSIVE, schedule=schedule, block=block)
+    try:
+        print(f"network order 5 schedule {schedule} block {block}", flush=True)
+        steps, _ = sim.run(1e9, 3)
+        assert steps == 3
+        qg, vg, _, _ = sim.numpy_state()
+    finally:
+        sim.close()
+    for s in range(S):
+        c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= ONE_STEP * 10, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= ONE_STEP * 10, s

@@ -27,7 +27,7 @@ def G():
     return grprec
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_trrs_acoustic_parity(G, order):
     n = 200
     dx, q, vl, vr = acoustic_case(n)

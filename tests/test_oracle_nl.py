@@ -237,7 +237,7 @@ def test_eigenvectors_of_the_flux_jacobian():
             np.testing.assert_allclose(A @ R[:, k], lam * R[:, k], atol=1e-7)
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_euler_nl_density_wave_equals_advection_nl(order):
     """With u and p constant the conserved state is affine in rho along the
     contact eigenvector, so in characteristic variables the acoustic fields
@@ -261,7 +261,7 @@ def test_euler_nl_density_wave_equals_advection_nl(order):
 def test_euler_nl_constant_state(bc):
     n = 20
     Q = I.prim_to_cons(np.full(n, 0.8), 0.3, 1.7)
-    for order in (2, 3, 4):
+    for order in (2, 3, 4, 5):
         c = oracle.cfg(oracle.EULER, order, bc=bc, recon=oracle.NONLINEAR)
         v = np.concatenate([Q, Q[:, :1]], axis=1)
         qn, vn, _, _, _ = oracle.run(c, 1.0 / n, Q, v, 0.0, 1.0, max_steps=5)
@@ -277,7 +277,7 @@ def test_euler_nl_periodic_conservation():
                        1.0 + 0.28 * np.sin(2 * np.pi * xm))
     v = I.prim_to_cons(1.0 + 0.2 * np.sin(2 * np.pi * xf), 0.3 * np.sin(2 * np.pi * xf),
                        1.0 + 0.28 * np.sin(2 * np.pi * xf))
-    for order in (2, 3, 4):
+    for order in (2, 3, 4, 5):
         c = oracle.cfg(oracle.EULER, order, recon=oracle.NONLINEAR)
         qn, _, _, k, _ = oracle.run(c, dx, q, v, 0.0, 1.0, max_steps=15)
         assert k == 15
