@@ -853,7 +853,11 @@ double orc_smax(const orc_cfg *cf, int n, const double *q) {
     orc_cons_to_prim(cf->gamma, Q, W);
     double c = sqrt(cf->gamma * W[2] / W[0]);
     double si = fabs(W[1]) + c;
-    if (!(si <= s)) s = si; /* NaN propagates */
+    if (isnan(si) || isnan(s)) {
+      s = NAN; /* a non-physical cell has no real wave speeds: keep the NaN */
+    } else if (si > s) {
+      s = si;
+    }
   }
   return s;
 }

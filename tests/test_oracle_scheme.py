@@ -320,3 +320,20 @@ def test_trrs_datum_shock_tube_runs_and_differs():
     d = np.abs(qt - qe).max()
     assert 1e-8 < d < 2e-2, d
     assert abs(qt.sum() - qe.sum()) < 1e-12 * np.abs(q).sum()  # both conservative
+
+
+def test_nonphysical_cell_is_reported_wherever_it_sits():
+    """S_max is the largest |lambda_j(Q_i)| over the cells (Sec. 4.1); a cell
+    with negative pressure has no real wave speeds, so the step reports a
+    non-physical state whether or not valid cells follow it."""
+    n = 30
+    dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
+    c = oracle.cfg(oracle.EULER, 3)
+    v = oracle.init_interfaces(c, vl, vr)
+    for k in (0, 11, n - 1):
+        qb = q.copy()
+        qb[2, k] = 0.5 * qb[1, k] ** 2 / qb[0, k] - 0.1
+        assert np.isnan(oracle.smax(c, qb))
+        with pytest.raises(oracle.OracleError) as ei:
+            oracle.step(c, dx, qb, v, 0.0, 1.0)
+        assert ei.value.code == oracle.E_NONPHYSICAL
