@@ -55,7 +55,9 @@ def test_workspace_bytes_valid_and_invalid(G):
     for bad in (dict(cfl=1.05), dict(cfl=0.0), dict(order=6), dict(order=1), dict(gamma=1.0),
                 dict(system=7), dict(bc=5), dict(cells=[100, 1]),
                 dict(bc=G.GRPREC_BC_PERIODIC, cells=[10, 10]),
-                dict(system=G.GRPREC_ADVECTION, lam=0.0)):
+                dict(system=G.GRPREC_ADVECTION, lam=0.0),
+                # 32-bit indexing limit: cells + segments <= INT_MAX / 3
+                dict(cells=[400_000_000, 400_000_000])):
         p, keep = _problem(G, **bad)
         assert G.grprec_workspace_bytes(p) == 0, bad
 
