@@ -317,7 +317,7 @@ def main():
                          " hardware-counter passes (network, advection 2^25, a 256 MB copy)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(independent segments would shard across GPUs with no communication).",
               file=sys.stderr)
         sys.exit(2)

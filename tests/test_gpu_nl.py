@@ -161,7 +161,7 @@ def test_euler_nl_network_parity(G, schedule, block):
 
 
 def test_sod_grprecnl_reports_failure(G):
-    """Both sides fail on Sod under this build's GRPrecNL readings: orders 3-4
+    """Both sides fail on Sod under these readings of GRPrecNL: orders 3-4
     at the first step, order 2 a few steps later."""
     dx, q, vl, vr = I.euler_shock_tube(100)
     for order in (2, 3, 4):

@@ -5,7 +5,7 @@ on polynomial data, the reduction to GRPrec for a dominant centred weight, the
 printed GRPrecNL convergence table (Sec. 4.2.3), the square-wave behaviour the
 paper describes (Sec. 4.2.2), the characteristic projection (eigenvectors of
 the flux Jacobian, reduction of Euler to advection), and the shock-tube
-behaviour under this build's readings."""
+behaviour under these readings of the paper."""
 import os
 
 import numpy as np
