@@ -45,6 +45,24 @@ __device__ __forceinline__ void wave_segmented_max(int seg, double val, unsigned
   }
 }
 
+// Whole-wave lane shifts of a double by DPP (wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (wave_prev) or lane l+1 (wave_next); the lane without a
+// source (0, resp. 63) keeps its own value.
+__device__ __forceinline__ double wave_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_next(double x) {
+  const long long b = __double_as_longlong(x);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);

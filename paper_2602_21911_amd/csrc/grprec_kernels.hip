@@ -634,28 +634,19 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     }
     return vin[k];
   };
-  // coefficients of cell k's polynomial; GRPrecNL at degree 4 also reads
-  // V_{k-3/2} and V_{k+3/2}, which beyond a transmissive end belong to the
-  // ghost cell (its constant average)
-  auto coeffs = [&](int k, double qk, double out[4]) {
-    if constexpr (NL) {
-      auto VG = [&](int j) -> double {
-        if (!a.periodic) {
-          if (j < 0) return qin[0];
-          if (j > n) return qin[n - 1];
-        }
-        return V(j);
-      };
-      adv_coeffs_nl<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), M == 4 ? VG(k - 1) : 0.0,
-                       M == 4 ? VG(k + 2) : 0.0, dx, a.nl_lambda_c, a.nl_eps, out);
-    } else {
-      adv_coeffs<M>(Q(k - 1), qk, Q(k + 1), V(k), V(k + 1), out);
+  // interface value j: wrapped when periodic; beyond a transmissive end the
+  // ghost cell's constant state (its average)
+  auto VG = [&](int j) -> double {
+    if (!a.periodic) {
+      if (j < 0) return qin[0];
+      if (j > n) return qin[n - 1];
     }
+    return V(j);
   };
   // A wave advances runs of ADV_RUN = 63 consecutive cells.  Its 64th lane
   // holds the run's upwind neighbour (lane 0 for lambda > 0, lane 63 for
   // lambda < 0), so every lane reconstructs one cell and the upwind lane's
-  // flux mean and end-of-step datum reach the next lane by a shuffle.  A block
+  // flux mean and end-of-step datum reach the next lane by a lane shift.  A block
   // takes chunks of 4 waves x ADV_PASSES runs.  Blocks are dispatched to the 8
   // XCDs round-robin, so block b works on chunk (b % 8) * per + b / 8:
   // consecutive chunks run on one XCD and the cache lines they share at their
@@ -674,24 +665,55 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     if (base >= n) break;                                 // uniform over the wave
     const int i = pos ? base + lane - 1 : base + lane;    // this lane's cell
     const bool own = pos ? lane >= 1 : lane < RUN;        // updated by this run
+    // Every lane within two cells of the domain holds the average of its cell
+    // and the value at the cell's left interface (wrapped when periodic; the
+    // ghost state beyond a transmissive end); a reconstruction takes its
+    // neighbours' values from the adjacent lanes, and only the wave's edge
+    // lanes load theirs.
+    // (cells -2 .. n+1 and interfaces -2 .. n+2 are what reconstructions of
+    // cells -1 .. n read; a single +-n wrap keeps them in range for n >= 2)
+    double qk = 0.0, vk = 0.0;
+    if (i >= -2 && i <= n + 2) {
+      qk = i <= n + 1 ? Q(i) : 0.0;
+      vk = VG(i);
+    }
+    double qm = wave_prev(qk), qp = wave_next(qk), vp = wave_next(vk);
+    double vm = 0.0, vpp = 0.0;
+    if constexpr (NL && M == 4) {
+      vm = wave_prev(vk);
+      vpp = wave_next(wave_next(vk));
+    }
     // the lane's flux mean over the swept interval and its datum; at i = -1
     // and i = n the upwind neighbour is the periodic image or the ghost cell
     // (a constant state: mean and point value are the end average)
     double mean_s = 0.0, pt_s = 0.0;
-    int k = -1;
-    if (i >= 0 && i < n) {
-      k = i;
-    } else if (i == -1 || i == n) {
-      if (a.periodic) {
-        k = i < 0 ? n - 1 : 0;
-      } else {
-        mean_s = pt_s = qin[i < 0 ? 0 : n - 1];
+    const bool recon = (i >= 0 && i < n) || (a.periodic && (i == -1 || i == n));
+    if (!recon && (i == -1 || i == n)) mean_s = pt_s = qk;
+    if (recon && !done) {
+      if (lane == 0) {
+        qm = Q(i - 1);
+        if constexpr (NL && M == 4) vm = VG(i - 1);
       }
-    }
-    if (k >= 0 && !done) {
-      const double qk = qin[k];
+      if (lane == 63) {
+        qp = Q(i + 1);
+        vp = VG(i + 1);
+      }
+      if constexpr (NL && M == 4) {
+        if (lane >= 62) vpp = VG(i + 2);
+      }
+      // interfaces 0 and n of a periodic domain are one interface: cell n-1
+      // reads its right value at n, cell 0 its left value at 0
+      double vl = vk;
+      if (a.periodic) {
+        if (i == -1) vp = vin[n];
+        if (i == n) vl = vin[0];
+      }
       double ac[4];
-      coeffs(k, qk, ac);
+      if constexpr (NL) {
+        adv_coeffs_nl<M>(qm, qk, qp, vl, vp, vm, vpp, dx, a.nl_lambda_c, a.nl_eps, ac);
+      } else {
+        adv_coeffs<M>(qm, qk, qp, vl, vp, ac);
+      }
       mean_s = qk;
       pt_s = qk;
 #pragma unroll
@@ -700,8 +722,8 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
         pt_s += ac[j] * Pin[j];
       }
     }
-    const double mean_u = pos ? __shfl_up(mean_s, 1, 64) : __shfl_down(mean_s, 1, 64);
-    const double pt_u = pos ? __shfl_up(pt_s, 1, 64) : __shfl_down(pt_s, 1, 64);
+    const double mean_u = pos ? wave_prev(mean_s) : wave_next(mean_s);
+    const double pt_u = pos ? wave_prev(pt_s) : wave_next(pt_s);
     if (!own || i < 0 || i >= n) continue;
     if (done) {
       qout[i] = qin[i];
@@ -709,7 +731,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       if (i == n - 1) vout[n] = vin[n];
       continue;
     }
-    const double qc = qin[i];
+    const double qc = qk;
     double qn;
     if (pos) {
       qn = qc - cn * (mean_s - mean_u);
