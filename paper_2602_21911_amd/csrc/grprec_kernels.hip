@@ -351,11 +351,10 @@ void euler_step(EulerArgs<M> a) {
     double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
     if (work && (useful || e == 0)) {
       const bool boundary = (!a.periodic) && (i == n - 1);
-      const bool gated = a.warm || a.guess == 1;
-      double pw = 0.0;
-      bool strong = false;
-#pragma unroll 1
-      for (int b = 0; b < NT; ++b) {
+      // Riemann problem at trace time b with Newton start pguess (0: PVRS),
+      // optionally testing the gate (learned start when mlp != nullptr);
+      // adds the flux sample or takes the datum
+      auto solve = [&](int b, double pguess, const float *mlp, bool test_gate) -> RSOut {
         double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
         double QR[3];
         if (boundary) {
@@ -363,20 +362,12 @@ void euler_step(EulerArgs<M> a) {
         } else {
           QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
         }
-        // the first time tests the interface's jump against the gate; above
-        // it the first time starts from the learned proposal and later times
-        // from the previous time's star pressure, below it (and without
-        // either option) every time starts from PVRS
-        const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
         RSOut o;
         if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
           err |= trrs_interact(G, QL, QR, o);
         else
-          err |= interact(G, QL, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
-                          mlp, a.gate, b == 0 && gated);
-        if (b == 0) strong = o.strong;
+          err |= interact(G, QL, QR, pguess, a.max_newton, a.newton_tol, o, mlp, a.gate, test_gate);
         st_mlp += o.learned ? 1 : 0;
-        pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
         if (b == 0 && a.hv.ring != nullptr && useful) {
@@ -399,6 +390,26 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll
           for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
         }
+        return o;
+      };
+      if (a.warm || a.guess == 1) {
+        // the first time tests the interface's jump against the gate; above
+        // it the first time starts from the learned proposal and later times
+        // from the previous time's star pressure, below it from PVRS
+        const RSOut o0 = solve(0, 0.0, a.guess == 1 ? a.mlp : nullptr, true);
+        if (__any(o0.strong)) {
+          double pw = o0.pstar;
+#pragma unroll 1
+          for (int b = 1; b < NT; ++b) pw = solve(b, o0.strong ? pw : 0.0, nullptr, false).pstar;
+        } else {  // no interface of the wave passed the gate: all from PVRS
+#pragma unroll 2
+          for (int b = 1; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
+        }
+      } else {
+        // every time starts from PVRS: the problems are independent, and two
+        // at a time give the scheduler independent work to interleave
+#pragma unroll 2
+        for (int b = 0; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
       }
       // flux and datum go to the right neighbour through this slot's own
       // right-trace column, which no other thread reads
