@@ -402,13 +402,13 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll 1
           for (int b = 1; b < NT; ++b) pw = solve(b, o0.strong ? pw : 0.0, nullptr, false).pstar;
         } else {  // no interface of the wave passed the gate: all from PVRS
-#pragma unroll 2
+#pragma unroll
           for (int b = 1; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
         }
       } else {
-        // every time starts from PVRS: the problems are independent, and two
-        // at a time give the scheduler independent work to interleave
-#pragma unroll 2
+        // every time starts from PVRS: the problems are independent, and the
+        // unrolled loop gives the scheduler independent work to interleave
+#pragma unroll
         for (int b = 0; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
       }
       // flux and datum go to the right neighbour through this slot's own
