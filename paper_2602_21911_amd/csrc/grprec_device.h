@@ -226,9 +226,7 @@ __device__ __forceinline__ int newton_pstar(const Gas &G, const Prim &L, const P
                                             Side &sl, Side &sr) {
   const double du = R.u - L.u;
   double pe = p;
-  int k = 1;
-  bool conv = false;
-  for (; k <= maxit; ++k) {
+  auto iterate = [&]() -> bool {
     pe = p;
     const double ip = rcp(p);
     side_eval(G, p, ip, L, sl);
@@ -237,9 +235,18 @@ __device__ __forceinline__ int newton_pstar(const Gas &G, const Prim &L, const P
     if (pn <= 0.0) pn = 0.5 * p;
     const bool stop = 2.0 * fabs(pn - p) <= tol * (pn + p);
     p = pn;
-    if (stop) {
-      conv = true;
-      break;
+    return stop;
+  };
+  // the first iteration, which is the last for most problems, outside the
+  // loop: straight-line code that independent solves can interleave
+  bool conv = iterate();
+  int k = 1;
+  if (!conv) {
+    for (k = 2; k <= maxit; ++k) {
+      if (iterate()) {
+        conv = true;
+        break;
+      }
     }
   }
   const double dp = p - pe;
