@@ -264,17 +264,37 @@ void euler_step(EulerArgs<M> a) {
                     a4 * T.phi[k][3];
       }
       }
-      // Picard iteration of the space-time Galerkin equations
+      // Picard iteration of the space-time Galerkin equations, from the data
+      // held constant in time.  In the first sweep the nodal fluxes and their
+      // space derivative therefore do not depend on the time node, and the
+      // time solve reduces to the row sums of K^-1 W.
       double qh[3][N][N];
-#pragma unroll
-      for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int x = 0; x < N; ++x)
-#pragma unroll
-          for (int y = 0; y < N; ++y) qh[v][x][y] = w[v][x];
       bool conv = false;
       int it = 1;
-      for (; it <= a.max_picard; ++it) {
+      {
+        double F1[3][N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) euler_flux(G, w[0][x], w[1][x], w[2][x], F1[0][x], F1[1][x], F1[2][x]);
+        double diff = 0.0, nrm = 0.0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            double Gd = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) Gd += T.D[x][k] * F1[v][k];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+              const double nv = w[v][x] - nu * (T.KWs[b] * Gd);
+              diff = fmax(diff, fabs(nv - w[v][x]));
+              nrm = fmax(nrm, fabs(nv));
+              qh[v][x][b] = nv;
+            }
+          }
+        }
+        conv = diff <= a.picard_tol * (1.0 + nrm);
+      }
+      if (!conv) for (it = 2; it <= a.max_picard; ++it) {
         double F[3][N][N];
 #pragma unroll
         for (int x = 0; x < N; ++x)

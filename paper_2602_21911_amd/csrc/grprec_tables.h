@@ -91,6 +91,7 @@ struct Predictor {
   double g[N], w[N];
   double D[N][N];
   double KW[N][N];
+  double KWs[N];     // row sums of KW (the time solve of a time-constant argument)
   double l0[N], l1[N];
   double phi[N][4];  // xi, xi^2 - 1/12, xi^3, xi^4 - 1/80 at xi = g_a - 1/2
 };
@@ -129,6 +130,10 @@ constexpr Predictor<M> predictor() {
   }
   for (int b = 0; b < N; ++b)
     for (int l = 0; l < N; ++l) P.KW[b][l] = K[b][N + l] * P.w[l];
+  for (int b = 0; b < N; ++b) {
+    P.KWs[b] = 0.0;
+    for (int l = 0; l < N; ++l) P.KWs[b] += P.KW[b][l];
+  }
   for (int a = 0; a < N; ++a) {
     for (int k = 0; k < N; ++k) P.D[a][k] = lag_d<N>(P.g, k, P.g[a]);
     P.l0[a] = lag<N>(P.g, a, 0.0);
