@@ -127,3 +127,61 @@ def test_riemann_batch_million_sampled(G):
             assert abs(ps[k] - p_ref) <= 1e-12 * p_ref, k
         else:
             assert it[k] == rc, (k, it[k], rc)
+
+
+def test_network_full_size_learned_start(G):
+    """The benchmark's headline form: the full network with the learned Newton
+    start (random network weights; gate -1, so every interface's first problem
+    starts from the network) equals the oracle on sampled segments."""
+    net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
+    rng = np.random.default_rng(4)
+    P = rng.normal(scale=0.3, size=1325)
+    P[1313:1319] = rng.normal(scale=0.1, size=6)
+    P[1319:1325] = rng.uniform(0.5, 2.0, size=6)
+    params = torch.from_numpy(P.astype(np.float32)).cuda()
+    steps = 3
+    sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                       bc=G.GRPREC_BC_TRANSMISSIVE, guess=G.GRPREC_GUESS_MLP, mlp_params=params,
+                       mlp_gate=-1.0, schedule=G.GRPREC_SCHED_AUTO)
+    try:
+        G.grprec_enable_stats(sim.h, True)
+        done, _ = sim.run(1e9, steps)
+        st = G.grprec_get_stats(sim.h)
+        assert done == steps
+        qg, vg, _, _ = sim.numpy_state()
+    finally:
+        sim.close()
+    assert st["mlp_guesses"] > 0
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    for s in sorted(set(rng.choice(len(net.n_cells), 40, replace=False).tolist())):
+        c0, c1 = int(net.cell_off[s]), int(net.cell_off[s + 1])
+        v = oracle.init_interfaces(c, net.vl[:, c0 + s:c1 + s + 1], net.vr[:, c0 + s:c1 + s + 1])
+        qr, vr, _, kr, _ = oracle.run(c, net.dx[s], net.q[:, c0:c1], v, 0.0, 1e9, steps)
+        assert rel_linf(qg[:, c0:c1], qr) <= 1e-11, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr) <= 1e-11, s
+
+
+@pytest.mark.parametrize("datum", [0, 1])
+def test_tube_network_full_size(G, datum):
+    """The benchmark's tube network (10^4 shock tubes, GRPrecNL order 3,
+    autotuned schedule), exact or two-rarefaction datum: sampled tubes after
+    5 steps equal the oracle."""
+    net = I.tube_network(n_seg=10000, seed=I.SEED_TUBE_NETWORK)
+    steps = 5
+    sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                       bc=G.GRPREC_BC_TRANSMISSIVE, recon=G.GRPREC_RECON_NL, datum=datum,
+                       schedule=G.GRPREC_SCHED_AUTO)
+    try:
+        done, _ = sim.run(1e9, steps)
+        assert done == steps
+        qg, vg, _, _ = sim.numpy_state()
+    finally:
+        sim.close()
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR, datum=datum)
+    rng = np.random.default_rng(8 + datum)
+    for s in sorted(set(rng.choice(len(net.n_cells), 40, replace=False).tolist())):
+        c0, c1 = int(net.cell_off[s]), int(net.cell_off[s + 1])
+        v = oracle.init_interfaces(c, net.vl[:, c0 + s:c1 + s + 1], net.vr[:, c0 + s:c1 + s + 1])
+        qr, vr, _, kr, _ = oracle.run(c, net.dx[s], net.q[:, c0:c1], v, 0.0, 1e9, steps)
+        assert rel_linf(qg[:, c0:c1], qr) <= 1e-10, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr) <= 1e-10, s
