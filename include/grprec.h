@@ -122,8 +122,8 @@ typedef struct {
                           interface's first Riemann problem above which the learned and
                           warm starts are taken; below it Newton starts from PVRS
                           (default 0.1; negative: always) */
-  int warm_start;      /* 1: at interfaces above the gate, later Riemann problems start
-                          from the previous time's p* (implied by GUESS_MLP) */
+  int warm_start;      /* 1: at interfaces above the gate, the later Riemann problems start
+                          from the first time's p* (implied by GUESS_MLP) */
   int schedule;        /* GRPREC_SCHED_* (Euler) */
   int block;           /* workgroup size 64, 128 or 256 (0 = choose) */
   int recon;           /* GRPREC_RECON_* */

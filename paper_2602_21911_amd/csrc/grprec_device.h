@@ -327,9 +327,10 @@ __device__ __forceinline__ void sample_at_zero(const Gas &G, const Prim &L, cons
 // 6 -> 32 -> 32 -> 1 tanh network, float32.  Weights are read with uniform
 // (wave-wide) addresses, so they arrive through the scalar cache.
 __device__ __forceinline__ float mlp_tanh(float x) {
-  // tanh(x) = 1 - 2 / (exp(2x) + 1), saturating cleanly for large |x|
-  float e = __expf(2.0f * x);
-  return 1.0f - 2.0f / (e + 1.0f);
+  // tanh(x) = 1 - 2 / (exp(2x) + 1), saturating cleanly for large |x|; the
+  // hardware reciprocal (1 ulp) instead of a correctly rounded division
+  const float e = __expf(2.0f * x);
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
 __device__ __forceinline__ void mlp_features(double g, double rl, double ul, double pl, double rr,
@@ -350,7 +351,7 @@ __device__ __forceinline__ float mlp_eval(const float *__restrict__ P, const flo
   const float *mean = P + 1313, *stdv = P + 1319;
   float x[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) x[i] = (xin[i] - mean[i]) / stdv[i];
+  for (int i = 0; i < 6; ++i) x[i] = (xin[i] - mean[i]) * __builtin_amdgcn_rcpf(stdv[i]);
   float h1[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) {

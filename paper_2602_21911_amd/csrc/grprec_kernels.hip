@@ -412,25 +412,17 @@ void euler_step(EulerArgs<M> a) {
         }
         return o;
       };
-      if (a.warm || a.guess == 1) {
-        // the first time tests the interface's jump against the gate; above
-        // it the first time starts from the learned proposal and later times
-        // from the previous time's star pressure, below it from PVRS
-        const RSOut o0 = solve(0, 0.0, a.guess == 1 ? a.mlp : nullptr, true);
-        if (__any(o0.strong)) {
-          double pw = o0.pstar;
-#pragma unroll 1
-          for (int b = 1; b < NT; ++b) pw = solve(b, o0.strong ? pw : 0.0, nullptr, false).pstar;
-        } else {  // no interface of the wave passed the gate: all from PVRS
+      // With gating (learned or warm starts) the first time tests the
+      // interface's jump against the gate; above it the first time starts from
+      // the learned proposal and the later times from the first time's star
+      // pressure, below it (and without gating) every time starts from PVRS.
+      // The later times are independent of each other, and the unrolled loop
+      // gives the scheduler that independent work.
+      const bool gated = a.warm || a.guess == 1;
+      const RSOut o0 = solve(0, 0.0, (gated && a.guess == 1) ? a.mlp : nullptr, gated);
+      const double pg = o0.strong ? o0.pstar : 0.0;
 #pragma unroll
-          for (int b = 1; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
-        }
-      } else {
-        // every time starts from PVRS: the problems are independent, and the
-        // unrolled loop gives the scheduler independent work to interleave
-#pragma unroll
-        for (int b = 0; b < NT; ++b) (void)solve(b, 0.0, nullptr, false);
-      }
+      for (int b = 1; b < NT; ++b) (void)solve(b, pg, nullptr, false);
       // flux and datum go to the right neighbour through this slot's own
       // right-trace column, which no other thread reads
 #pragma unroll
@@ -455,9 +447,11 @@ void euler_step(EulerArgs<M> a) {
         else
           err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
                           mlp, a.gate, b == 0 && gated);
-        if (b == 0) strong = o.strong;
+        if (b == 0) {  // later times start from the first time's p* above the gate
+          strong = o.strong;
+          pw = o.pstar;
+        }
         st_mlp += o.learned ? 1 : 0;
-        pw = o.pstar;
         st_rs += 1;
         st_newton += o.iters;
         if (b < N) {
