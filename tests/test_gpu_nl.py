@@ -229,3 +229,45 @@ def test_tube_network_parity(G, guess, order):
         c0, c1 = full.cell_off[s], full.cell_off[s + 1]
         assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
+
+
+@pytest.mark.parametrize("gate", [0.1, -1.0])
+def test_warm_start_parity(G, gate):
+    """Warm starts (later Riemann problems of an interface start from the
+    first time's star pressure above the gate; gate -1: everywhere) change
+    only Newton's starting point, so shock tubes (GRPrecNL) and the smooth
+    network equal the oracle, which starts every problem from PVRS."""
+    net = I.tube_network(n_seg=50)
+    S = len(net.n_cells)
+    c = _ocfg(oracle.EULER, 3, oracle.TRANSMISSIVE, 10.0)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 10)
+    sim = _sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+               G.GRPREC_BC_TRANSMISSIVE, 10.0, warm_start=1, mlp_gate=gate,
+               schedule=G.GRPREC_SCHED_FLAT_TILES, block=128)
+    try:
+        print(f"warm start tubes gate {gate}", flush=True)
+        steps, _ = sim.run(1e9, 10)
+        assert steps == 10
+        qg, vg, _, _ = sim.numpy_state()
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-12)
+    finally:
+        sim.close()
+    for s in range(S):
+        c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
+    smooth = network_case(30, seed=13, nmax=300)
+    S = len(smooth.n_cells)
+    cl = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(cl, smooth.vl, smooth.vr)
+    qr, vr_, tr, _ = oracle.run_segments(cl, smooth.cell_off, smooth.dx, smooth.q, v0, np.zeros(S), 1e9, 4)
+    sim = G.Simulation(G.GRPREC_EULER, 3, smooth.n_cells, smooth.lengths, smooth.q, smooth.vl, smooth.vr,
+                       bc=G.GRPREC_BC_TRANSMISSIVE, warm_start=1, mlp_gate=gate,
+                       schedule=G.GRPREC_SCHED_PACKED, block=64)
+    try:
+        sim.run(1e9, 4)
+        qg, vg, _, _ = sim.numpy_state()
+    finally:
+        sim.close()
+    assert rel_linf(qg, qr) <= 1e-10 and rel_linf(vg, vr_) <= 1e-10
