@@ -600,7 +600,7 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
 }
 
 #ifndef ADV_PASSES
-#define ADV_PASSES 2  // runs per wave per block chunk
+#define ADV_PASSES 4  // runs per wave per block chunk (4 measured best of 1, 2, 4, 6, 8)
 #endif
 #define ADV_RUN 63    // cells a wave updates per run (64 lanes, one upwind overlap)
 
