@@ -1,7 +1,9 @@
 """Pins of the oracle's exact Euler Riemann solver by properties of the exact
 solution that do not use the pressure function: integral conservation of the
-self-similar solution, Galilean and scaling invariance, symmetry, the
-two-rarefaction closed form, the vacuum condition and guess independence."""
+self-similar solution, the Rankine-Hugoniot conditions across shocks and the
+isentrope and Riemann invariant across rarefactions, Galilean and scaling
+invariance, symmetry, the two-rarefaction closed form, the vacuum condition
+and guess independence."""
 import numpy as np
 import pytest
 
@@ -30,11 +32,11 @@ def _sample(WL, WR, s):
 
 
 CASES = [
-    ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),         # shock tube: rarefaction, contact, shock
-    ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),          # two rarefactions
-    ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01)),       # strong shock
-    ((5.99924, 19.5975, 460.894), (5.99242, -6.19633, 46.0950)),  # colliding shocks
-    ((1.0, 0.75, 1.0), (0.125, 0.0, 0.1)),        # sonic rarefaction
+    ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),         # Sod data (Sec. 4.3.2): rarefaction, contact, shock
+    ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),          # 123-problem data (Sec. 4.3.2): two rarefactions
+    ((1.0, 0.0, 800.0), (1.2, 0.0, 0.02)),        # strong shock
+    ((6.0, 19.0, 450.0), (5.5, -6.5, 50.0)),      # colliding shocks
+    ((1.0, 0.8, 1.0), (0.15, 0.0, 0.12)),         # transonic rarefaction
     ((0.3, -1.2, 0.02), (2.0, 0.4, 30.0)),
 ]
 
@@ -59,6 +61,33 @@ def test_integral_conservation(WL, WR):
     # (at most three) discontinuities; a wrong star state is off by O(1)
     ds = 2 * X / n
     assert np.all(np.abs(lhs - rhs) < 1.5 * scale * ds), (lhs, rhs, ds)
+
+
+@pytest.mark.parametrize("WL,WR", CASES)
+def test_jump_relations_of_both_nonlinear_waves(WL, WR):
+    """Star states sampled just beside the contact: across a shock (p* above
+    the outer pressure) mass, momentum and energy fluxes jump consistently
+    with one shock speed (Rankine-Hugoniot); across a rarefaction the
+    entropy p/rho^g and the outgoing Riemann invariant u -/+ 2c/(g-1) are
+    carried through."""
+    ps, us, _, _ = oracle.riemann(G, WL, WR)
+    d = 1e-9 * (1.0 + abs(us))
+    for side, W, Ws in ((-1, np.array(WL), _sample(WL, WR, us - d)),
+                        (1, np.array(WR), _sample(WL, WR, us + d))):
+        assert abs(Ws[2] - ps) <= 1e-12 * ps and abs(Ws[1] - us) <= 1e-9 * (1 + abs(us))
+        if ps > W[2]:  # shock
+            q0, q1 = _cons(W), _cons(Ws)
+            f0, f1 = _flux(W), _flux(Ws)
+            S = (f1[0] - f0[0]) / (q1[0] - q0[0])  # shock speed from mass conservation
+            for k in (1, 2):
+                scale = abs(f0[k]) + abs(f1[k]) + abs(S) * (abs(q0[k]) + abs(q1[k]))
+                assert abs((f1[k] - f0[k]) - S * (q1[k] - q0[k])) <= 1e-11 * scale, (k, S)
+            assert side * (S - us) > 0  # the shock lies on its own side of the contact
+        else:  # rarefaction
+            c, cs = np.sqrt(G * W[2] / W[0]), np.sqrt(G * Ws[2] / Ws[0])
+            assert abs(Ws[2] / Ws[0] ** G - W[2] / W[0] ** G) <= 1e-11 * W[2] / W[0] ** G
+            inv = lambda u, cc: u - side * 2.0 * cc / (G - 1.0)
+            assert abs(inv(Ws[1], cs) - inv(W[1], c)) <= 1e-11 * (abs(W[1]) + c)
 
 
 @pytest.mark.parametrize("WL,WR", CASES)
