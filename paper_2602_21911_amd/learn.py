@@ -144,6 +144,11 @@ def evaluate(P, wl, wr, gamma: float = 1.4, gate: float = -1.0):
     ok = (it0 > 0) & (it1 > 0)
     a = it0[ok].double()
     b = it1[ok].double()
+    # fallback: the solver takes PVRS when pbar exp(y) is not a positive finite
+    # double, i.e. y non-finite or outside the range of exp in double precision
+    x, _ = G.grprec_mlp_features(wl, wr, gamma=gamma)
+    y = G.grprec_mlp_forward(P, x)
+    fallback = (~torch.isfinite(y)) | (y > 709.0) | (y < -745.0)
     rel = ((ps1[ok] - ps0[ok]).abs() / ps0[ok]).max().item() if ok.any() else 0.0
     q = lambda t, f: float(torch.quantile(t, f).item())
     return {
@@ -152,6 +157,7 @@ def evaluate(P, wl, wr, gamma: float = 1.4, gate: float = -1.0):
         "pvrs_mean": float(a.mean().item()), "pvrs_p50": q(a, 0.5), "pvrs_p99": q(a, 0.99),
         "mlp_mean": float(b.mean().item()), "mlp_p50": q(b, 0.5), "mlp_p99": q(b, 0.99),
         "max_rel_pstar_diff": rel,
+        "fallback_rate": float(fallback.double().mean().item()),
     }
 
 

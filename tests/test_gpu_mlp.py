@@ -87,6 +87,7 @@ def test_training_gains_over_pvrs(G):
     ev = learn.evaluate(P, torch.from_numpy(WL).cuda(), torch.from_numpy(WR).cuda())
     assert ev["mlp_mean"] < ev["pvrs_mean"], ev
     assert ev["max_rel_pstar_diff"] <= 1e-11, ev
+    assert 0.0 <= ev["fallback_rate"] < 1e-3, ev
     # the learned start leaves every star pressure at the oracle's value
     ps, it = G.grprec_riemann_batch(torch.from_numpy(WL[:500]).cuda(), torch.from_numpy(WR[:500]).cuda(),
                                     guess=G.GRPREC_GUESS_MLP, mlp_params=P)
