@@ -184,7 +184,8 @@ constexpr double kWeak = 1e-5;
 
 __device__ __forceinline__ void side_eval(const Gas &G, double p, double ip, const Prim &K, Side &s) {
   const double d = (p - K.p) * K.ip;
-  if (fabs(d) <= kWeak) {
+  // weak waves dominate smooth flows: the other branches are laid out apart
+  if (__builtin_expect(fabs(d) <= kWeak, 1)) {
     s.rare = false;  // w is not carried on this path
     s.w = 0.0;
     s.f = (K.c * G.inv_g) * d * fma(-G.k2, d, 1.0);
@@ -241,7 +242,7 @@ __device__ __forceinline__ int newton_pstar(const Gas &G, const Prim &L, const P
   // loop: straight-line code that independent solves can interleave
   bool conv = iterate();
   int k = 1;
-  if (!conv) {
+  if (__builtin_expect(!conv, 0)) {
     for (k = 2; k <= maxit; ++k) {
       if (iterate()) {
         conv = true;
