@@ -175,6 +175,43 @@ def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0):
             "traffic": traffic}
 
 
+def bench_small_case(G, torch, I, cfl=0.9):
+    """Advection of sin 2 pi x on 100 periodic cells, order 3, to t = 1 (112
+    steps): a latency-bound case, timed as whole runs through grprec_run
+    (graph-captured chunks of steps) and as one grprec_step call per step
+    (no host synchronisation between steps)."""
+    import oracle
+    n = 100
+    dx, q, vl, vr = I.adv_sin2pi(n)
+    out = {"workload": "advection sin 2 pi x, 100 periodic cells, order 3, CFL %g, t_end 1" % cfl}
+    for form in ("graph", "eager"):
+        best = None
+        for _rep in range(5):
+            sim = G.Simulation(G.GRPREC_ADVECTION, 3, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC,
+                               cfl=cfl)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if form == "graph":
+                    steps, _ = sim.run(1.0)
+                else:
+                    for _k in range(steps):
+                        sim.step(1.0)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                assert sim.state()[3] == 1.0
+            finally:
+                sim.close()
+            best = sec if best is None else min(best, sec)
+        out[form] = {"steps": steps, "us_per_step": 1e6 * best / steps, "seconds": best}
+    c = oracle.cfg(oracle.ADVECTION, 3, cfl=cfl)
+    v = oracle.init_interfaces(c, vl, vr)
+    t0 = time.perf_counter()
+    _q, _v, _t, k, _st = oracle.run(c, dx, q, v, 0.0, 1.0)
+    out["oracle_us_per_step"] = 1e6 * (time.perf_counter() - t0) / k
+    return out
+
+
 def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon, datum=0):
     """Rate of one batched form, and its solver counters over the same steps
     (counted in a second, untimed run)."""
@@ -265,6 +302,39 @@ def cpu_baseline(net, steps: int):
     return {"value": cells * steps / sec, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"all {S} segments ({int(cells)} cells), {steps} steps each, serial C oracle",
             "seconds": sec}
+
+
+def cpu_all_cores(net, steps: int):
+    """Context figure: the same serial oracle run on contiguous groups of
+    segments in host threads (the C call releases the interpreter lock)."""
+    import concurrent.futures as cf
+    import oracle
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    S = len(net.n_cells)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    bounds = np.linspace(0, S, 4 * threads + 1).astype(int)
+    jobs = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        c0, c1 = int(net.cell_off[a]), int(net.cell_off[b])
+        jobs.append((net.cell_off[a:b + 1] - c0, net.dx[a:b], net.q[:, c0:c1], v0[:, c0 + a:c1 + b]))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda j: oracle.run_segments(c, j[0], j[1], j[2], j[3], np.zeros(len(j[1])), 1e9, steps), jobs))
+    sec = time.perf_counter() - t0
+    cells = float(net.n_cells.sum())
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": cells * steps / sec, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {S} segments, {steps} steps each, {len(jobs)} groups of segments over"
+                      f" {threads} threads", "seconds": sec, "cpu_model": model,
+            "visible_cpus": len(os.sched_getaffinity(0))}
 
 
 def counters_run(G, torch, I):
@@ -392,15 +462,18 @@ def main():
     if mlp is not None:
         line["mlp"] = mlp
     if not args.no_extras:
-        line["advection"] = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25),
+        line["advection"] = [bench_advection(G, torch, 1 << 20), bench_advection(G, torch, 1 << 22),
+                             bench_advection(G, torch, 1 << 25),
                              bench_advection(G, torch, 1 << 25, order=5),
                              bench_advection(G, torch, 1 << 25, recon=1),
                              bench_advection(G, torch, 1 << 25, order=5, recon=1)]
         line["euler_single_domain"] = bench_euler_single(G, torch, 1 << 22)
         line["network_variants"] = bench_network_variants(G, torch)
         line["tube_network"] = bench_tube_network(G, torch, params)
+        line["small_case"] = bench_small_case(G, torch, I)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)
+        line["cpu_all_cores"] = cpu_all_cores(net, args.cpu_steps)
     print(json.dumps(line), flush=True)
 
 

@@ -66,7 +66,7 @@ static Layout layout(const grprec_problem *p, long long tc) {
   L.t = o; o = align256(o + sizeof(double) * 3 * S);
   L.smax = o; o = align256(o + sizeof(unsigned long long) * 3 * S);
   L.max_tiles = (p->system == GRPREC_EULER) ? tc / 62 + S + 2 : 0;
-  L.tiles = o; o = align256(o + sizeof(int4) * L.max_tiles);
+  L.tiles = o; o = align256(o + sizeof(Tile) * L.max_tiles);
   L.snap_doubles = (p->system == GRPREC_EULER && p->schedule == GRPREC_SCHED_AUTO)
                        ? nvar * (2 * tc + S) + 6 * S
                        : 0;
@@ -91,7 +91,7 @@ struct grprec_handle {
   Layout L;
   Ctl *ctl;
   Seg seg;
-  int4 *tiles;
+  Tile *tiles;
   int ntiles;
   int schedule, block, grid;
   std::vector<int> dom_tile0;  // per-domain first tile (per-domain schedule)
@@ -132,7 +132,28 @@ static int err_code(unsigned bits) {
 }
 
 // ------------------------------------------------------------ tiles
-static std::vector<int4> build_tiles(grprec_handle *h, int schedule, int block) {
+// Descriptor of the tile of `count` cells from `start`, first domain z, last w.
+static Tile make_tile(int start, int count, int z, int w, const std::vector<int> &off, bool periodic) {
+  Tile d;
+  std::memset(&d, 0, sizeof(d));
+  d.start = start;
+  d.count = count;
+  d.w = w;
+  d.cl = start > off[z] ? start - 1 : (periodic ? off[z + 1] - 1 : -1);
+  const int last = start + count - 1;
+  d.cr = last + 1 < off[w + 1] ? last + 1 : (periodic ? off[w] : -1);
+  int s = z;
+  for (int e = 0; e < 256; ++e) {
+    if ((e & 63) == 0) d.base[e >> 6] = s;
+    if (e >= 2 && e <= count && start + e - 1 == off[s + 1]) {
+      ++s;
+      d.first[e >> 6] |= 1ull << (e & 63);
+    }
+  }
+  return d;
+}
+
+static std::vector<Tile> build_tiles(grprec_handle *h, int schedule, int block) {
   const int T = block - 2;
   std::vector<int4> t;
   const int S = h->S;
@@ -184,7 +205,11 @@ static std::vector<int4> build_tiles(grprec_handle *h, int schedule, int block) 
     }
     h->dom_tile0[S] = (int)t.size();
   }
-  return t;
+  const bool periodic = h->p.bc == GRPREC_BC_PERIODIC;
+  std::vector<Tile> d;
+  d.reserve(t.size());
+  for (const int4 &r : t) d.push_back(make_tile(r.x, r.y, r.z, r.w, off, periodic));
+  return d;
 }
 
 static int euler_occ(int M, int block, bool nl, int *occ) {
@@ -199,9 +224,9 @@ static int euler_occ(int M, int block, bool nl, int *occ) {
 }
 
 static int apply_schedule(grprec_handle *h, int schedule, int block) {
-  std::vector<int4> t = build_tiles(h, schedule, block);
+  std::vector<Tile> t = build_tiles(h, schedule, block);
   if ((long long)t.size() > h->L.max_tiles) return GRPREC_E_INVALID;
-  HIPCHK(hipMemcpyAsync(h->tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->tiles, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->ntiles = (int)t.size();
   h->schedule = schedule;
@@ -454,7 +479,7 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   h->seg.t = (double *)(h->work + L.t);
   h->seg.smax = (unsigned long long *)(h->work + L.smax);
   h->seg.S = h->S;
-  h->tiles = (int4 *)(h->work + L.tiles);
+  h->tiles = (Tile *)(h->work + L.tiles);
   int rc = GRPREC_OK;
   auto fail = [&](int code) {
     grprec_destroy(h);

@@ -23,10 +23,10 @@ __device__ __forceinline__ double powpos(double x, double e) { return exp2(e * l
 
 // ---------------------------------------------------------------- reductions
 // Per-domain maximum over one wave: lanes hold (seg, val) with seg
-// non-decreasing over the lanes that take part (seg >= 0); the first lane of
-// each run of equal seg does one atomicMax on base[seg].  Values are
-// non-negative doubles, whose bit patterns order like the values.
-__device__ __forceinline__ void wave_segmented_max(int seg, double val, unsigned long long *base) {
+// non-decreasing over the lanes that take part (seg >= 0).  Returns true on
+// the first lane of each run of equal seg, which receives the run's maximum
+// as the bits of a non-negative double (bit patterns order like the values).
+__device__ __forceinline__ bool wave_segmented_lead(int seg, double val, unsigned long long &bits) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -34,15 +34,20 @@ __device__ __forceinline__ void wave_segmented_max(int seg, double val, unsigned
     int os = __shfl_down(seg, d, 64);
     if (lane + d < 64 && os == seg) val = nanmax(val, ov);
   }
-  int prev = __shfl_up(seg, 1, 64);
-  if (seg >= 0 && (lane == 0 || prev != seg)) {
-    // the target only grows while it accumulates, so a run whose maximum does
-    // not exceed the value already there has nothing to add; skipping it keeps
-    // a long domain's many waves from queueing on one address
-    const unsigned long long bits = dbits(val);
-    if (__hip_atomic_load(base + seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits)
-      atomicMax(base + seg, bits);
-  }
+  const int prev = __shfl_up(seg, 1, 64);
+  bits = dbits(val);
+  return seg >= 0 && (lane == 0 || prev != seg);
+}
+
+// One atomicMax per run on base[seg].  The target only grows while it
+// accumulates, so a run whose maximum does not exceed the value already there
+// has nothing to add; skipping it keeps a long domain's many waves from
+// queueing on one address.
+__device__ __forceinline__ void wave_segmented_max(int seg, double val, unsigned long long *base) {
+  unsigned long long bits;
+  if (wave_segmented_lead(seg, val, bits) &&
+      __hip_atomic_load(base + seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits)
+    atomicMax(base + seg, bits);
 }
 
 // Whole-wave lane shifts of a double by DPP (wave_shr:1 / wave_shl:1): lane l

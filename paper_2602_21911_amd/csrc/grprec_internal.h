@@ -89,6 +89,20 @@ struct Seg {
   int S;
 };
 
+// One tile of the batched Euler step.  A block holds `count` consecutive cells
+// from `start` in slots 1..count and halo cells in slots 0 and count+1.  Every
+// slot's domain follows from the descriptor without further reads: bit k of
+// first[j] marks slot 64j+k (k >= 2 overall) as the first cell of a domain,
+// base[j] is the domain of the slots of word j before its first mark, and the
+// right halo slot lies in domain w.
+struct alignas(16) Tile {
+  int start, count;
+  int cl, cr;                  // halo cells of slots 0 and count+1, -1 when none
+  int w, pad[3];               // domain of the last owned cell
+  int base[4];
+  unsigned long long first[4];
+};
+
 struct Harvest {
   double *ring;                // [cap][7] or null
   long long cap;
@@ -99,7 +113,7 @@ template <int M>
 struct EulerArgs {
   double *q0, *q1, *v0, *v1;
   int tc, ti;                  // total cells, total interfaces (SoA strides)
-  const int4 *tiles;           // (first cell, count, first domain, last domain)
+  const Tile *tiles;
   int ntiles;
   Seg seg;
   Ctl *ctl;

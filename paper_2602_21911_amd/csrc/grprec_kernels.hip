@@ -20,20 +20,13 @@ namespace grp {
 // domains.
 __device__ __forceinline__ void domain_dt(double cfl, double dx, double S, double t, double t_end,
                                           double &dt, double &t_new, bool &done) {
+  // selects rather than branches: S is then read with the slot's other data
+  // instead of behind the time test
+  const double d = cfl * dx / S;
   done = !(t < t_end);
-  if (done) {
-    dt = 0.0;
-    t_new = t;
-    return;
-  }
-  double d = cfl * dx / S;
-  if (d >= t_end - t) {
-    dt = t_end - t;
-    t_new = t_end;
-  } else {
-    dt = d;
-    t_new = t + d;
-  }
+  const bool last = d >= t_end - t;
+  dt = done ? 0.0 : (last ? t_end - t : d);
+  t_new = done ? t : (last ? t_end : t + d);
 }
 
 // Step launched when no domain is active: carry the slot forward unchanged.
@@ -72,9 +65,11 @@ __device__ __forceinline__ double pick(const double (&t)[N], int b) {
 }
 
 // ============================================================ Euler step
-// Waves per SIMD the register allocation must leave room for (1 = no limit).
+// Waves per SIMD the register allocation must leave room for (1 = no limit):
+// two up to order 3, whose kernels fit 256 registers per lane; order 4 and 5
+// hold too many predictor unknowns for that.
 #ifndef GRPREC_EULER_WAVES
-#define GRPREC_EULER_WAVES 1
+#define GRPREC_EULER_WAVES(M) ((M) <= 2 ? 2 : 1)
 #endif
 
 // AIR: gamma is 1.4 and the gas constants are compile-time values.
@@ -82,7 +77,7 @@ __device__ __forceinline__ double pick(const double (&t)[N], int b) {
 // TR: end-of-step datum by the two-rarefaction solver (Sec. 4.1); a run-time
 // branch in the Riemann loop would cost registers on every path.
 template <int M, int B, bool AIR, bool NL, bool TR>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES)))
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES(M))))
 void euler_step(EulerArgs<M> a) {
   constexpr int N = M + 1;   // nodes per direction
   constexpr int NT = M + 2;  // trace times: N Gauss-Legendre times and tau = 1
@@ -114,50 +109,83 @@ void euler_step(EulerArgs<M> a) {
   unsigned err = 0;
   unsigned st_rs = 0, st_newton = 0, st_sweeps = 0, st_cells = 0, st_mlp = 0;
 
+  // this wave's words of a tile descriptor
+  struct LaneTile {
+    int start, count, cl, cr, w, base;
+    unsigned long long first;
+  };
+  const int wj = (B > 64) ? (e >> 6) : 0;
+  auto lane_tile = [&](int k) {
+    const Tile *d = a.tiles + k;
+    LaneTile r;
+    r.start = d->start; r.count = d->count; r.cl = d->cl; r.cr = d->cr;
+    r.w = d->w;
+    r.base = d->base[wj];
+    r.first = d->first[wj];
+    return r;
+  };
+  // the next tile's descriptor is read one tile ahead
+  LaneTile nx = {0, 0, -1, -1, 0, 0, 0ull};
+  if ((int)blockIdx.x < a.ntiles) nx = lane_tile(blockIdx.x);
+  // S_max of the new states: a tile's run maxima are compared with the
+  // accumulating target, read at the end of the tile, at the head of the next
+  // one, so that read's latency overlaps the next tile's own reads
+  unsigned long long *const acc = a.seg.smax + s1 * a.seg.S;
+  bool pend = false;
+  int pseg = 0;
+  unsigned long long pbits = 0, pseen = 0;
+
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const int4 td = a.tiles[tile];
-    const int start = td.x, count = td.y;
-    // ---- which cell this slot holds
+    const LaneTile td = nx;
+    if (tile + (int)gridDim.x < a.ntiles) nx = lane_tile(tile + gridDim.x);
+    const int start = td.start, count = td.count;
+    // ---- which cell this slot holds, and its domain
     bool valid = false, useful = false;
-    int c = 0, s = td.z;
+    int c = 0;
     if (e >= 1 && e <= count) {
       c = start + e - 1;
-      s = (td.z == td.w) ? td.z : find_domain(a.seg.cell_off, c, td.z, td.w);
       valid = useful = true;
     } else if (e == 0) {
-      s = td.z;
-      const int off = a.seg.cell_off[s], end = a.seg.cell_off[s + 1];
-      if (start > off) { c = start - 1; valid = true; }
-      else if (a.periodic) { c = end - 1; valid = true; }
+      c = td.cl;
+      valid = c >= 0;
     } else if (e == count + 1) {
-      s = td.w;
-      const int off = a.seg.cell_off[s], end = a.seg.cell_off[s + 1];
-      const int last = start + count - 1;
-      if (last + 1 < end) { c = last + 1; valid = true; }
-      else if (a.periodic) { c = off; valid = true; }
+      c = td.cr;
+      valid = c >= 0;
     }
+    const int s = (e == count + 1) ? td.w : td.base + __popcll(td.first & ((2ull << (e & 63)) - 1ull));
+    // every read of the slot depends on (c, s) alone, so they are issued together
     int off = 0, n = 1, i = 0, io = 0;
     double dx = 1.0, dt = 0.0, t_new = 0.0, nu = 0.0, t = 0.0;
     bool done = true;
+    double q0[3], vl0[3], vr0[3];
     if (valid) {
       off = a.seg.cell_off[s];
       n = a.seg.cell_off[s + 1] - off;
-      i = c - off;
-      io = off + s;
       dx = a.seg.dx[s];
       t = a.seg.t[slot * a.seg.S + s];
       const double S = bitsd(a.seg.smax[slot * a.seg.S + s]);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        q0[v] = qin[v * tc + c];
+        vl0[v] = vin[v * ti + c + s];
+        vr0[v] = vin[v * ti + c + s + 1];
+      }
+      i = c - off;
+      io = off + s;
       domain_dt(a.cfl, dx, S, t, t_end, dt, t_new, done);
       nu = dt / dx;
     }
     const bool work = valid && !done;
-
-    // ---- load, reconstruct, predict
-    double q0[3];
-    if (valid) {
+    if (pend && pseen < pbits) atomicMax(acc + pseg, pbits);
+    if (useful && !work) {  // a domain past its end time carries its data over
 #pragma unroll
-      for (int v = 0; v < 3; ++v) q0[v] = qin[v * tc + c];
+      for (int v = 0; v < 3; ++v) {
+        vout[v * ti + c + s + 1] = vr0[v];
+        if (i == 0) vout[v * ti + c + s] = vl0[v];
+      }
     }
+
+    // ---- reconstruct, predict
     if (work) {
       int im = i - 1, ip = i + 1;
       if (a.periodic) {
@@ -183,8 +211,8 @@ void euler_step(EulerArgs<M> a) {
             dm[v] = qin[v * tc + off + im] - q0[v];
             dp[v] = qin[v * tc + off + ip] - q0[v];
           }
-          dl[v] = vin[v * ti + io + i] - q0[v];
-          dr[v] = vin[v * ti + io + i + 1] - q0[v];
+          dl[v] = vl0[v] - q0[v];
+          dr[v] = vr0[v] - q0[v];
           if constexpr (M == 4) {
             // V_{i-3/2} and V_{i+3/2}: wrapped when periodic; beyond a
             // transmissive end they belong to the ghost cell, a constant
@@ -238,7 +266,7 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         const double qc = q0[v];
-        const double vl = vin[v * ti + io + i], vr = vin[v * ti + io + i + 1];
+        const double vl = vl0[v], vr = vr0[v];
         const double DI = vr - vl, SI = vl + vr - 2.0 * qc;
         double a1, a2 = 0.0, a3 = 0.0, a4 = 0.0;
         if (M == 1) {
@@ -489,11 +517,7 @@ void euler_step(EulerArgs<M> a) {
         }
       } else {
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          qn[v] = q0[v];
-          vout[v * ti + io + i + 1] = vin[v * ti + io + i + 1];
-          if (i == 0) vout[v * ti + io] = vin[v * ti + io];
-        }
+        for (int v = 0; v < 3; ++v) qn[v] = q0[v];
       }
 #pragma unroll
       for (int v = 0; v < 3; ++v) qout[v * tc + c] = qn[v];
@@ -511,9 +535,12 @@ void euler_step(EulerArgs<M> a) {
         if (t_new < t_end) atomicAdd(&ctl->active[s1], 1);
       }
     }
-    wave_segmented_max(seg_tag, smax_i, a.seg.smax + s1 * a.seg.S);
+    pend = wave_segmented_lead(seg_tag, smax_i, pbits);
+    pseg = seg_tag;
+    pseen = pend ? __hip_atomic_load(acc + seg_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
     __syncthreads();
   }
+  if (pend && pseen < pbits) atomicMax(acc + pseg, pbits);
   if (err) atomicOr(&ctl->err, err);
   if (stats) {
     const unsigned long long r0 = wave_sum_u64(st_rs), r1 = wave_sum_u64(st_newton),
