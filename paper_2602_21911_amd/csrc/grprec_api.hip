@@ -132,84 +132,15 @@ static int err_code(unsigned bits) {
 }
 
 // ------------------------------------------------------------ tiles
-// Descriptor of the tile of `count` cells from `start`, first domain z, last w.
-static Tile make_tile(int start, int count, int z, int w, const std::vector<int> &off, bool periodic) {
-  Tile d;
-  std::memset(&d, 0, sizeof(d));
-  d.start = start;
-  d.count = count;
-  d.w = w;
-  d.cl = start > off[z] ? start - 1 : (periodic ? off[z + 1] - 1 : -1);
-  const int last = start + count - 1;
-  d.cr = last + 1 < off[w + 1] ? last + 1 : (periodic ? off[w] : -1);
-  int s = z;
-  for (int e = 0; e < 256; ++e) {
-    if ((e & 63) == 0) d.base[e >> 6] = s;
-    if (e >= 2 && e <= count && start + e - 1 == off[s + 1]) {
-      ++s;
-      d.first[e >> 6] |= 1ull << (e & 63);
-    }
-  }
-  return d;
-}
+static_assert((int)kSegmentTiles == GRPREC_SCHED_SEGMENT_TILES && (int)kFlatTiles == GRPREC_SCHED_FLAT_TILES &&
+                  (int)kPacked == GRPREC_SCHED_PACKED,
+              "tile orders follow the schedule constants");
 
 static std::vector<Tile> build_tiles(grprec_handle *h, int schedule, int block) {
-  const int T = block - 2;
-  std::vector<int4> t;
-  const int S = h->S;
-  const std::vector<int> &off = h->cell_off;
-  auto seg_of = [&](int c) {
-    return int(std::upper_bound(off.begin(), off.end(), c) - off.begin()) - 1;
-  };
-  if (schedule == GRPREC_SCHED_FLAT_TILES) {
-    for (long long st = 0; st < h->tc; st += T) {
-      int cnt = (int)std::min<long long>(T, h->tc - st);
-      t.push_back(make_int4((int)st, cnt, seg_of((int)st), seg_of((int)(st + cnt - 1))));
-    }
-  } else if (schedule == GRPREC_SCHED_PACKED) {
-    int cur_start = -1, cur_cnt = 0, cur_s0 = 0;
-    auto flush = [&](int last_seg) {
-      if (cur_cnt > 0) t.push_back(make_int4(cur_start, cur_cnt, cur_s0, last_seg));
-      cur_cnt = 0;
-      cur_start = -1;
-    };
-    for (int s = 0; s < S; ++s) {
-      const int n = off[s + 1] - off[s];
-      if (n > T) {
-        flush(s - 1);
-        int pieces = (n + T - 1) / T;
-        int base = n / pieces, extra = n % pieces, st = off[s];
-        for (int k = 0; k < pieces; ++k) {
-          int cnt = base + (k < extra ? 1 : 0);
-          t.push_back(make_int4(st, cnt, s, s));
-          st += cnt;
-        }
-      } else {
-        if (cur_cnt + n > T) flush(s - 1);
-        if (cur_cnt == 0) {
-          cur_start = off[s];
-          cur_s0 = s;
-        }
-        cur_cnt += n;
-      }
-    }
-    flush(S - 1);
-  } else {  // segment tiles (also the per-domain schedule)
-    h->dom_tile0.assign(S + 1, 0);
-    for (int s = 0; s < S; ++s) {
-      h->dom_tile0[s] = (int)t.size();
-      for (int st = off[s]; st < off[s + 1]; st += T) {
-        int cnt = std::min(T, off[s + 1] - st);
-        t.push_back(make_int4(st, cnt, s, s));
-      }
-    }
-    h->dom_tile0[S] = (int)t.size();
-  }
-  const bool periodic = h->p.bc == GRPREC_BC_PERIODIC;
-  std::vector<Tile> d;
-  d.reserve(t.size());
-  for (const int4 &r : t) d.push_back(make_tile(r.x, r.y, r.z, r.w, off, periodic));
-  return d;
+  // the per-domain launches use segment tiles
+  const int order = (schedule == GRPREC_SCHED_FLAT_TILES || schedule == GRPREC_SCHED_PACKED)
+                        ? schedule : (int)kSegmentTiles;
+  return plan_tiles(h->cell_off, order, block, h->p.bc == GRPREC_BC_PERIODIC, h->dom_tile0);
 }
 
 static int euler_occ(int M, int block, bool nl, int *occ) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "grprec_tiles.h"
 
 namespace grp {
 
@@ -87,20 +88,6 @@ struct Seg {
   double *t;                   // [3][S] time per slot
   unsigned long long *smax;    // [3][S] S_max per slot (bits of a non-negative double)
   int S;
-};
-
-// One tile of the batched Euler step.  A block holds `count` consecutive cells
-// from `start` in slots 1..count and halo cells in slots 0 and count+1.  Every
-// slot's domain follows from the descriptor without further reads: bit k of
-// first[j] marks slot 64j+k (k >= 2 overall) as the first cell of a domain,
-// base[j] is the domain of the slots of word j before its first mark, and the
-// right halo slot lies in domain w.
-struct alignas(16) Tile {
-  int start, count;
-  int cl, cr;                  // halo cells of slots 0 and count+1, -1 when none
-  int w, pad[3];               // domain of the last owned cell
-  int base[4];
-  unsigned long long first[4];
 };
 
 struct Harvest {
