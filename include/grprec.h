@@ -183,11 +183,13 @@ int grprec_set_state(grprec_handle *h, int current, double t, int64_t steps);
 int grprec_get_schedule(grprec_handle *h, int *schedule, int *block);
 int grprec_set_schedule(grprec_handle *h, int schedule, int block);
 
-/* Time each schedule candidate for `steps` steps from the current state and
- * keep the fastest one whose result is bitwise equal to the first candidate's;
- * the state is restored.  Writes per-candidate milliseconds per step into
- * ms_out[n_max] (candidate order: schedules 1..3 x blocks 64,128,256), and the
- * number written into *n_out. */
+/* Time each schedule candidate for `steps` steps from the current state (the
+ * fastest of three runs) and keep the fastest candidate whose result is
+ * bitwise equal to the first candidate's; the state is restored.  Writes
+ * per-candidate milliseconds per step into ms_out[n_max] (candidate order:
+ * schedules 1..3 x blocks 64,128,256; a single domain tries segment tiles
+ * only; negative when the result differed), and the number written into
+ * *n_out. */
 int grprec_autotune(grprec_handle *h, int steps, double *ms_out, int n_max, int *n_out);
 
 /* Counters accumulated since init when count_stats is on: Riemann solves,

@@ -641,16 +641,23 @@ int grprec_autotune(grprec_handle *h, int steps, double *ms_out, int n_max, int 
       if (rc) break;
       rc = eager_step(h);  // warm-up (also first touch of code)
       if (rc) break;
-      rc = restore();
-      if (rc) break;
-      rc = prologue(h, std::numeric_limits<double>::infinity());
-      if (rc) break;
-      HIPCHK(hipEventRecord(e0, h->stream));
-      for (int k = 0; k < steps && rc == GRPREC_OK; ++k) rc = eager_step(h);
-      HIPCHK(hipEventRecord(e1, h->stream));
-      HIPCHK(hipEventSynchronize(e1));
+      // the fastest of three timed runs from the same state: a few steps
+      // of a fraction of a millisecond each vary by a few per cent
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      for (int rep = 0; rep < 3 && rc == GRPREC_OK; ++rep) {
+        rc = restore();
+        if (rc) break;
+        rc = prologue(h, std::numeric_limits<double>::infinity());
+        if (rc) break;
+        HIPCHK(hipEventRecord(e0, h->stream));
+        for (int k = 0; k < steps && rc == GRPREC_OK; ++k) rc = eager_step(h);
+        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float r = 0.f;
+        HIPCHK(hipEventElapsedTime(&r, e0, e1));
+        if (rep == 0 || r < ms) ms = r;
+      }
+      if (rc) break;
       // digest of the resulting state
       rc = read_ctl(h);
       if (rc) break;
