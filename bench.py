@@ -304,6 +304,19 @@ def cpu_baseline(net, steps: int):
             "seconds": sec}
 
 
+def segment_groups(net, v, n_groups: int):
+    """Contiguous groups of a network's segments as independent networks:
+    (cell offsets from 0, dx, cell averages, interface values), the interface
+    arrays holding one value more per segment than the cell arrays."""
+    S = len(net.n_cells)
+    bounds = np.linspace(0, S, n_groups + 1).astype(int)
+    jobs = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        c0, c1 = int(net.cell_off[a]), int(net.cell_off[b])
+        jobs.append((net.cell_off[a:b + 1] - c0, net.dx[a:b], net.q[:, c0:c1], v[:, c0 + a:c1 + b]))
+    return bounds, jobs
+
+
 def cpu_all_cores(net, steps: int):
     """Context figure: the same serial oracle run on contiguous groups of
     segments in host threads (the C call releases the interpreter lock)."""
@@ -313,11 +326,7 @@ def cpu_all_cores(net, steps: int):
     v0 = oracle.init_interfaces(c, net.vl, net.vr)
     S = len(net.n_cells)
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    bounds = np.linspace(0, S, 4 * threads + 1).astype(int)
-    jobs = []
-    for a, b in zip(bounds[:-1], bounds[1:]):
-        c0, c1 = int(net.cell_off[a]), int(net.cell_off[b])
-        jobs.append((net.cell_off[a:b + 1] - c0, net.dx[a:b], net.q[:, c0:c1], v0[:, c0 + a:c1 + b]))
+    _, jobs = segment_groups(net, v0, 4 * threads)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
         list(ex.map(lambda j: oracle.run_segments(c, j[0], j[1], j[2], j[3], np.zeros(len(j[1])), 1e9, steps), jobs))
