@@ -1,6 +1,12 @@
-"""Build libgrprec.so in-tree with hipcc for gfx950."""
+"""Build libgrprec.so in-tree with hipcc for gfx950.
+
+Each translation unit is compiled to an object in parallel (the Euler step is
+instantiated per degree in its own unit), then the objects are linked into
+the shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -8,22 +14,46 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgrprec.so")
-SOURCES = ["grprec_api.hip", "grprec_kernels.hip", "grprec_mlp.hip"]
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+OBJDIR = os.path.join(HERE, "_build")
+SOURCES = ["grprec_api.hip", "grprec_kernels.hip", "grprec_mlp.hip", "grprec_euler_m1.hip",
+           "grprec_euler_m2.hip", "grprec_euler_m3.hip", "grprec_euler_m4.hip"]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _jobs() -> int:
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tag = "_".join(d.replace("=", "-") for d in defines)
+    objdir = os.path.join(OBJDIR, tag) if tag else OBJDIR
+    os.makedirs(objdir, exist_ok=True)
+    dflags = [f"-D{d}" for d in defines]
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc, *FLAGS, *dflags, "-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
+        if verbose:
+            sys.stderr.write(res.stderr)
+        os.replace(obj + ".tmp", obj)
+        return obj
+
+    with cf.ThreadPoolExecutor(_jobs()) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"
-    cmd = [hipcc, *FLAGS, *[f"-D{d}" for d in defines], "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libgrprec.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc failed linking libgrprec.so")
     os.replace(tmp, out)
     return out
 

@@ -1,0 +1,560 @@
+// grprec_euler.h -- the fused Euler step kernel of the GRPrec finite-volume
+// scheme and its launch wrappers, as templates over the degree; each
+// grprec_euler_m<M>.hip translation unit instantiates one degree.
+//
+// One launch advances every domain by one step:
+//   dt from S_max (eq. dt-FV) -> GRPrec reconstruction (Sec. 3.1) -> DET
+//   space-time predictor -> Riemann problems at the Gauss-Legendre times of the
+//   flux integral (eq. numfluxes) and at tau = dt (next step's interface data)
+//   -> conservative update (eq. eq_finite_volume) -> S_max of the new state.
+// FP64 throughout; no matrix cores: the work is a per-cell stencil, not a
+// dense contraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "grprec_device.h"
+#include "grprec_internal.h"
+#include "grprec_step_common.h"
+#include "grprec_tables.h"
+
+namespace grp {
+
+// ============================================================ Euler step
+// Waves per SIMD the register allocation must leave room for (1 = no limit):
+// two up to order 3, whose kernels fit 256 registers per lane; order 4 and 5
+// hold too many predictor unknowns for that.
+#ifndef GRPREC_EULER_WAVES
+#define GRPREC_EULER_WAVES(M) ((M) <= 2 ? 2 : 1)
+#endif
+
+// AIR: gamma is 1.4 and the gas constants are compile-time values.
+// NL: GRPrecNL reconstruction (Sec. 3.3-3.4) instead of GRPrec (Sec. 3.1).
+// TR: end-of-step datum by the two-rarefaction solver (Sec. 4.1); a run-time
+// branch in the Riemann loop would cost registers on every path.
+template <int M, int B, bool AIR, bool NL, bool TR>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES(M))))
+void euler_step(EulerArgs<M> a) {
+  constexpr int N = M + 1;   // nodes per direction
+  constexpr int NT = M + 2;  // trace times: N Gauss-Legendre times and tau = 1
+  constexpr tab::Predictor<M> T = tab::predictor<M>();
+  __shared__ double sTL[3 * NT][B];
+  __shared__ double sTR[3 * NT][B];
+
+  Ctl *ctl = a.ctl;
+  const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
+  if (ctl->active[slot] == 0) {
+    carry_slot(a.seg, ctl, slot);
+    return;
+  }
+  const int cur = ctl->cur[slot];
+  const double *__restrict__ qin = cur ? a.q1 : a.q0;
+  double *__restrict__ qout = cur ? a.q0 : a.q1;
+  const double *__restrict__ vin = cur ? a.v1 : a.v0;
+  double *__restrict__ vout = cur ? a.v0 : a.v1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->cur[s1] = 1 - cur;
+    ctl->steps[s1] = ctl->steps[slot] + 1;
+    ctl->active[s2] = 0;
+  }
+  const double t_end = ctl->t_end;
+  const bool stats = ctl->stats_on != 0;
+  const Gas G = AIR ? kAir : a.gas;
+  const int e = threadIdx.x;
+  const int tc = a.tc, ti = a.ti;
+  unsigned err = 0;
+  unsigned st_rs = 0, st_newton = 0, st_sweeps = 0, st_cells = 0, st_mlp = 0;
+
+  // this wave's words of a tile descriptor
+  struct LaneTile {
+    int start, count, cl, cr, w, base;
+    unsigned long long first;
+  };
+  const int wj = (B > 64) ? (e >> 6) : 0;
+  auto lane_tile = [&](int k) {
+    const Tile *d = a.tiles + k;
+    LaneTile r;
+    r.start = d->start; r.count = d->count; r.cl = d->cl; r.cr = d->cr;
+    r.w = d->w;
+    r.base = d->base[wj];
+    r.first = d->first[wj];
+    return r;
+  };
+  // the next tile's descriptor is read one tile ahead
+  LaneTile nx = {0, 0, -1, -1, 0, 0, 0ull};
+  if ((int)blockIdx.x < a.ntiles) nx = lane_tile(blockIdx.x);
+  // S_max of the new states: a tile's run maxima are compared with the
+  // accumulating target, read at the end of the tile, at the head of the next
+  // one, so that read's latency overlaps the next tile's own reads
+  unsigned long long *const acc = a.seg.smax + s1 * a.seg.S;
+  bool pend = false;
+  int pseg = 0;
+  unsigned long long pbits = 0, pseen = 0;
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const LaneTile td = nx;
+    if (tile + (int)gridDim.x < a.ntiles) nx = lane_tile(tile + gridDim.x);
+    const int start = td.start, count = td.count;
+    // ---- which cell this slot holds, and its domain
+    bool valid = false, useful = false;
+    int c = 0;
+    if (e >= 1 && e <= count) {
+      c = start + e - 1;
+      valid = useful = true;
+    } else if (e == 0) {
+      c = td.cl;
+      valid = c >= 0;
+    } else if (e == count + 1) {
+      c = td.cr;
+      valid = c >= 0;
+    }
+    const int s = (e == count + 1) ? td.w : td.base + __popcll(td.first & ((2ull << (e & 63)) - 1ull));
+    // every read of the slot depends on (c, s) alone, so they are issued together
+    int off = 0, n = 1, i = 0, io = 0;
+    double dx = 1.0, dt = 0.0, t_new = 0.0, nu = 0.0, t = 0.0;
+    bool done = true;
+    double q0[3], vl0[3], vr0[3];
+    if (valid) {
+      off = a.seg.cell_off[s];
+      n = a.seg.cell_off[s + 1] - off;
+      dx = a.seg.dx[s];
+      t = a.seg.t[slot * a.seg.S + s];
+      const double S = bitsd(a.seg.smax[slot * a.seg.S + s]);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        q0[v] = qin[v * tc + c];
+        vl0[v] = vin[v * ti + c + s];
+        vr0[v] = vin[v * ti + c + s + 1];
+      }
+      i = c - off;
+      io = off + s;
+      domain_dt(a.cfl, dx, S, t, t_end, dt, t_new, done);
+      nu = dt / dx;
+    }
+    const bool work = valid && !done;
+    if (pend && pseen < pbits) atomicMax(acc + pseg, pbits);
+    if (useful && !work) {  // a domain past its end time carries its data over
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        vout[v * ti + c + s + 1] = vr0[v];
+        if (i == 0) vout[v * ti + c + s] = vl0[v];
+      }
+    }
+
+    // ---- reconstruct, predict
+    if (work) {
+      int im = i - 1, ip = i + 1;
+      if (a.periodic) {
+        if (im < 0) im += n;
+        if (ip >= n) ip -= n;
+      } else {
+        if (im < 0) im = 0;
+        if (ip >= n) ip = n - 1;
+      }
+      double w[3][N];
+      if constexpr (NL) {
+        // GRPrecNL in characteristic variables: differences of the stencil
+        // data to the cell mean are projected with the left eigenvectors at
+        // the cell mean, each field is reconstructed as a scalar, and the
+        // coefficients are projected back
+        double Lm[3][3], Rm[3][3];
+        euler_eigen(G, q0, Lm, Rm);
+        double dm[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0}, dl[3], dr[3];
+        double dll[3] = {0.0, 0.0, 0.0}, drr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          if constexpr (M >= 2) {
+            dm[v] = qin[v * tc + off + im] - q0[v];
+            dp[v] = qin[v * tc + off + ip] - q0[v];
+          }
+          dl[v] = vl0[v] - q0[v];
+          dr[v] = vr0[v] - q0[v];
+          if constexpr (M == 4) {
+            // V_{i-3/2} and V_{i+3/2}: wrapped when periodic; beyond a
+            // transmissive end they belong to the ghost cell, a constant
+            // state equal to the end average
+            int kl = i - 1, kr = i + 2;
+            double vll, vrr;
+            if (a.periodic) {
+              if (kl < 0) kl += n;
+              if (kr > n) kr -= n;
+              vll = vin[v * ti + io + kl];
+              vrr = vin[v * ti + io + kr];
+            } else {
+              vll = kl >= 0 ? vin[v * ti + io + kl] : qin[v * tc + off];
+              vrr = kr <= n ? vin[v * ti + io + kr] : qin[v * tc + off + n - 1];
+            }
+            dll[v] = vll - q0[v];
+            drr[v] = vrr - q0[v];
+          }
+        }
+        double ac[3][M];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          double del[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            del[0] = fma(Lm[f][v], dm[v], del[0]);
+            del[2] = fma(Lm[f][v], dp[v], del[2]);
+            del[3] = fma(Lm[f][v], dl[v], del[3]);
+            del[4] = fma(Lm[f][v], dr[v], del[4]);
+            if constexpr (M == 4) {
+              del[5] = fma(Lm[f][v], dll[v], del[5]);
+              del[6] = fma(Lm[f][v], drr[v], del[6]);
+            }
+          }
+          double aC[M];
+          grprec_from_diffs<M>(del[0], del[2], del[3], del[4], aC);
+          nl_mix<M>(aC, del, dx, a.nl_lambda_c, a.nl_eps, ac[f]);
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          double cv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int j = 0; j < M; ++j)
+            cv[j] = Rm[v][0] * ac[0][j] + Rm[v][1] * ac[1][j] + Rm[v][2] * ac[2][j];
+#pragma unroll
+          for (int k = 0; k < N; ++k)
+            w[v][k] = q0[v] + cv[0] * T.phi[k][0] + cv[1] * T.phi[k][1] + cv[2] * T.phi[k][2] +
+                      cv[3] * T.phi[k][3];
+        }
+      } else {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const double qc = q0[v];
+        const double vl = vl0[v], vr = vr0[v];
+        const double DI = vr - vl, SI = vl + vr - 2.0 * qc;
+        double a1, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+        if (M == 1) {
+          a1 = DI;
+        } else if (M == 2) {
+          a1 = DI;
+          a2 = 3.0 * SI;
+        } else {
+          const double qm = qin[v * tc + off + im], qp = qin[v * tc + off + ip];
+          const double DC = qp - qm, SC = qp + qm - 2.0 * qc;
+          a1 = 1.25 * DI - 0.125 * DC;
+          a3 = 0.5 * DC - DI;
+          if (M == 3) {
+            a2 = (3.0 * SI + 18.0 * SC) * (1.0 / 37.0);
+          } else {
+            a2 = 3.75 * SI - 0.125 * SC;
+            a4 = (5.0 / 12.0) * SC - 2.5 * SI;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+          w[v][k] = qc + a1 * T.phi[k][0] + a2 * T.phi[k][1] + a3 * T.phi[k][2] +
+                    a4 * T.phi[k][3];
+      }
+      }
+      // Picard iteration of the space-time Galerkin equations, from the data
+      // held constant in time.  In the first sweep the nodal fluxes and their
+      // space derivative therefore do not depend on the time node, and the
+      // time solve reduces to the row sums of K^-1 W.
+      double qh[3][N][N];
+      bool conv = false;
+      int it = 1;
+      {
+        double F1[3][N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) euler_flux(G, w[0][x], w[1][x], w[2][x], F1[0][x], F1[1][x], F1[2][x]);
+        double diff = 0.0, nrm = 0.0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            double Gd = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) Gd += T.D[x][k] * F1[v][k];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+              const double nv = w[v][x] - nu * (T.KWs[b] * Gd);
+              diff = fmax(diff, fabs(nv - w[v][x]));
+              nrm = fmax(nrm, fabs(nv));
+              qh[v][x][b] = nv;
+            }
+          }
+        }
+        conv = diff <= a.picard_tol * (1.0 + nrm);
+      }
+      if (!conv) for (it = 2; it <= a.max_picard; ++it) {
+        double F[3][N][N];
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+#pragma unroll
+          for (int y = 0; y < N; ++y)
+            euler_flux(G, qh[0][x][y], qh[1][x][y], qh[2][x][y], F[0][x][y], F[1][x][y], F[2][x][y]);
+        double diff = 0.0, nrm = 0.0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            double Gd[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              double acc = 0.0;
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc += T.D[x][k] * F[v][k][l];
+              Gd[l] = acc;
+            }
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+              double acc = 0.0;
+#pragma unroll
+              for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[l];
+              const double nv = w[v][x] - nu * acc;
+              // non-finite values do not stop the sweep here: they reach the
+              // traces and are caught by the physical-state checks
+              diff = fmax(diff, fabs(nv - qh[v][x][b]));
+              nrm = fmax(nrm, fabs(nv));
+              qh[v][x][b] = nv;
+            }
+          }
+        }
+        if (diff <= a.picard_tol * (1.0 + nrm)) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv) err |= ERR_PICARD;
+      st_sweeps += conv ? it : a.max_picard;
+      st_cells += 1;
+      // traces at xi = 0 and xi = 1, times g_b and 1, staged in LDS
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double l1sum = 0.0, r1sum = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          double l = 0.0, r = 0.0;
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            l += T.l0[x] * qh[v][x][b];
+            r += T.l1[x] * qh[v][x][b];
+          }
+          sTL[v * NT + b][e] = l;
+          sTR[v * NT + b][e] = r;
+        }
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          double at1 = 0.0;
+#pragma unroll
+          for (int b = 0; b < N; ++b) at1 += T.l1[b] * qh[v][x][b];
+          l1sum += T.l0[x] * at1;
+          r1sum += T.l1[x] * at1;
+        }
+        sTL[v * NT + N][e] = l1sum;
+        sTR[v * NT + N][e] = r1sum;
+      }
+    }
+    __syncthreads();
+
+    // ---- interface x_{i+1/2}: Riemann problems at the trace times.  At a
+    // transmissive end the outside data are a ghost cell holding the end
+    // cell's average, constant in space and time.
+    double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
+    if (work && (useful || e == 0)) {
+      const bool boundary = (!a.periodic) && (i == n - 1);
+      // Riemann problem at trace time b with Newton start pguess (0: PVRS),
+      // optionally testing the gate (learned start when mlp != nullptr);
+      // adds the flux sample or takes the datum
+      auto solve = [&](int b, double pguess, const float *mlp, bool test_gate) -> RSOut {
+        double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
+        double QR[3];
+        if (boundary) {
+          QR[0] = q0[0]; QR[1] = q0[1]; QR[2] = q0[2];
+        } else {
+          QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+        }
+        RSOut o;
+        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
+          err |= trrs_interact(G, QL, QR, o);
+        else
+          err |= interact(G, QL, QR, pguess, a.max_newton, a.newton_tol, o, mlp, a.gate, test_gate);
+        st_mlp += o.learned ? 1 : 0;
+        st_rs += 1;
+        st_newton += o.iters;
+        if (b == 0 && a.hv.ring != nullptr && useful) {
+          unsigned long long k = atomicAdd(a.hv.count, 1ull);
+          if ((long long)k < a.hv.cap) {
+            Prim L, R;
+            to_prim(G, QL[0], QL[1], QL[2], L);
+            to_prim(G, QR[0], QR[1], QR[2], R);
+            double *dst = a.hv.ring + 7 * k;
+            dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
+            dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
+            dst[6] = o.pstar;
+          }
+        }
+        if (b < N) {
+          const double wb = pick<N>(T.w, b);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) FR[v] += wb * o.F[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
+        }
+        return o;
+      };
+      // With gating (learned or warm starts) the first time tests the
+      // interface's jump against the gate; above it the first time starts from
+      // the learned proposal and the later times from the first time's star
+      // pressure, below it (and without gating) every time starts from PVRS.
+      // The later times are independent of each other, and the unrolled loop
+      // gives the scheduler that independent work.
+      const bool gated = a.warm || a.guess == 1;
+      const RSOut o0 = solve(0, 0.0, (gated && a.guess == 1) ? a.mlp : nullptr, gated);
+      const double pg = o0.strong ? o0.pstar : 0.0;
+#pragma unroll
+      for (int b = 1; b < NT; ++b) (void)solve(b, pg, nullptr, false);
+      // flux and datum go to the right neighbour through this slot's own
+      // right-trace column, which no other thread reads
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        sTR[v][e] = FR[v];
+        sTR[3 + v][e] = VR[v];
+      }
+    }
+    // left end of a transmissive domain: ghost average against the left trace
+    double FL[3] = {0.0, 0.0, 0.0}, VL[3] = {0.0, 0.0, 0.0};
+    if (work && useful && i == 0 && !a.periodic) {
+      const bool gated = a.warm || a.guess == 1;
+      double pw = 0.0;
+      bool strong = false;
+#pragma unroll 1
+      for (int b = 0; b < NT; ++b) {
+        double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
+        const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
+        RSOut o;
+        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
+          err |= trrs_interact(G, q0, QR, o);
+        else
+          err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
+                          mlp, a.gate, b == 0 && gated);
+        if (b == 0) {  // later times start from the first time's p* above the gate
+          strong = o.strong;
+          pw = o.pstar;
+        }
+        st_mlp += o.learned ? 1 : 0;
+        st_rs += 1;
+        st_newton += o.iters;
+        if (b < N) {
+          const double wb = pick<N>(T.w, b);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) FL[v] += wb * o.F[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) VL[v] = o.Q[v];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- conservative update and S_max of the new state
+    double smax_i = 0.0;
+    int seg_tag = -1;
+    if (useful) {
+      double qn[3];
+      if (work) {
+        if (i > 0 || a.periodic) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            FL[v] = sTR[v][e - 1];
+            VL[v] = sTR[3 + v][e - 1];
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) qn[v] = q0[v] - nu * (FR[v] - FL[v]);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) vout[v * ti + io + i + 1] = VR[v];
+        if (i == 0) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) vout[v * ti + io] = VL[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) qn[v] = q0[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 3; ++v) qout[v * tc + c] = qn[v];
+      Prim W;
+      if (!to_prim(G, qn[0], qn[1], qn[2], W)) {
+        err |= ERR_NONPHYS;
+        smax_i = __longlong_as_double(0x7ff8000000000000ll);
+      } else {
+        smax_i = fabs(W.u) + W.c;
+      }
+      seg_tag = s;
+      if (i == 0) {  // one thread per domain owns its scalars
+        a.seg.t[s1 * a.seg.S + s] = t_new;
+        a.seg.smax[s2 * a.seg.S + s] = 0ull;
+        if (t_new < t_end) atomicAdd(&ctl->active[s1], 1);
+      }
+    }
+    pend = wave_segmented_lead(seg_tag, smax_i, pbits);
+    pseg = seg_tag;
+    pseen = pend ? __hip_atomic_load(acc + seg_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
+    __syncthreads();
+  }
+  if (pend && pseen < pbits) atomicMax(acc + pseg, pbits);
+  if (err) atomicOr(&ctl->err, err);
+  if (stats) {
+    const unsigned long long r0 = wave_sum_u64(st_rs), r1 = wave_sum_u64(st_newton),
+                             r2 = wave_sum_u64(st_sweeps), r3 = wave_sum_u64(st_cells),
+                             r4 = wave_sum_u64(st_mlp);
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&ctl->stat[0], r0);
+      atomicAdd(&ctl->stat[1], r1);
+      atomicAdd(&ctl->stat[2], r2);
+      atomicAdd(&ctl->stat[3], r3);
+      atomicAdd(&ctl->stat[4], r4);
+    }
+  }
+}
+
+// ============================================================ launchers
+// (host-callable wrappers so that the API file needs no kernel templates)
+template <int M, int B, bool NL>
+static hipError_t launch_euler_mbn(const EulerArgs<M> &a, int grid, hipStream_t st) {
+  if (a.gas.g == kGammaAir) {
+    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, true, NL, true>), dim3(grid), dim3(B), 0, st, a);
+    else hipLaunchKernelGGL((euler_step<M, B, true, NL, false>), dim3(grid), dim3(B), 0, st, a);
+  } else {
+    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, false, NL, true>), dim3(grid), dim3(B), 0, st, a);
+    else hipLaunchKernelGGL((euler_step<M, B, false, NL, false>), dim3(grid), dim3(B), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int M, int B>
+static hipError_t launch_euler_mb(const EulerArgs<M> &a, int grid, bool nl, hipStream_t st) {
+  return nl ? launch_euler_mbn<M, B, true>(a, grid, st) : launch_euler_mbn<M, B, false>(a, grid, st);
+}
+
+template <int M>
+hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, bool nl, hipStream_t st) {
+  switch (block) {
+    case 64: return launch_euler_mb<M, 64>(a, grid, nl, st);
+    case 128: return launch_euler_mb<M, 128>(a, grid, nl, st);
+    case 256: return launch_euler_mb<M, 256>(a, grid, nl, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int M, int B>
+static hipError_t euler_occ_b(bool nl, int *blocks_per_cu) {
+  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true, false>, B, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false, false>, B, 0);
+}
+
+template <int M>
+hipError_t euler_occupancy(int block, bool nl, int *blocks_per_cu) {
+  switch (block) {
+    case 64: return euler_occ_b<M, 64>(nl, blocks_per_cu);
+    case 128: return euler_occ_b<M, 128>(nl, blocks_per_cu);
+    case 256: return euler_occ_b<M, 256>(nl, blocks_per_cu);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace grp
