@@ -34,7 +34,7 @@
  * Errors: every function returns GRPREC_OK (0) or a negative code.  Errors
  * raised inside kernels (non-physical states, vacuum, iteration caps) are
  * latched on the device and returned by the next call that synchronises
- * (grprec_step with dt_out, grprec_run, grprec_state).
+ * (grprec_step with dt_out, grprec_run, grprec_state, grprec_get_state).
  */
 #ifndef GRPREC_H
 #define GRPREC_H
@@ -127,10 +127,10 @@ typedef struct {
   int schedule;        /* GRPREC_SCHED_* (Euler) */
   int block;           /* workgroup size 64, 128 or 256 (0 = choose) */
   int recon;           /* GRPREC_RECON_* */
-  double nl_lambda_c;  /* GRPrecNL weight of the centred polynomial, (0, 1e30]
-                          (default 10 when 0; the paper prints 1e9, with which
-                          GRPrecNL equals GRPrec on smooth data, while its GRPrecNL
-                          results are reproduced with 10) */
+  double nl_lambda_c;  /* GRPrecNL weight lambda_C of the centred polynomial in eq. (omega),
+                          (0, 1e30]; default 1e9 when 0, the value Sec. 3.3 prints.  With
+                          it GRPrecNL equals GRPrec on smooth data; the printed GRPrecNL
+                          advection results (Sec. 4.2.3) are reproduced with 10 */
   double nl_eps;       /* GRPrecNL epsilon, [1e-30, 1] (default 1e-14 when 0) */
   int datum;           /* GRPREC_DATUM_* (Euler only) */
 } grprec_problem;
@@ -145,87 +145,144 @@ typedef struct {
   size_t work_bytes;
 } grprec_buffers;
 
-/* Bytes of device workspace needed for this problem (0 on invalid input). */
+/* Bytes of device workspace needed for this problem (0 on invalid input).
+ * The workspace holds the control block, the per-domain tables (cell offsets,
+ * dx, times and S_max of eq. dt-FV), the tile lists and, with schedule AUTO,
+ * an autotuning snapshot of one state. */
 size_t grprec_workspace_bytes(const grprec_problem *p);
 
-/* Validate the problem, build the plans, compute the first-step interface data
- * and the first S_max on `hip_stream` (a hipStream_t; NULL = default stream).
- * Time starts at 0.  With schedule AUTO the Euler tile schedule is autotuned
- * here (a few timed steps on a snapshot that is restored afterwards). */
+/* Set-up of the scheme of Sec. 2 on N uniform cells per domain (the grid of
+ * Sec. 2): validates the problem (order 2..5 as in Sec. 3.1, 0 < C_CFL <= 1 as
+ * the Courant limit of Sec. 4.1 and its table of methods), builds the plans,
+ * computes the first-step interface data (the Riemann solution between the
+ * one-sided limits of the initial condition; the paper is silent on the first
+ * step) and the first S_max (Sec. 4.1) on `hip_stream` (a hipStream_t; NULL =
+ * default stream).  Time starts at 0.  With schedule AUTO the Euler tile
+ * schedule is autotuned here (a few timed steps on a snapshot that is
+ * restored afterwards).  *out receives a handle owned by the caller until
+ * grprec_destroy; on error *out is NULL and nothing is left allocated. */
 int grprec_init(grprec_handle **out, const grprec_problem *p, const grprec_buffers *b,
                 void *hip_stream);
 
-/* One time step, clipped so that no domain passes t_stop.  Domains already at
- * t_stop do not move.  dt_out != NULL synchronises the stream and returns the
- * step of domain 0 (latched device errors are returned then). */
+/* One time step of eq. (eq_finite_volume), Sec. 2: dt from eq. (dt-FV) with
+ * S_max of Sec. 4.1 per domain, GRPrec (Sec. 3.1) or GRPrecNL (Sec. 3.3-3.4)
+ * reconstruction from the cell averages and the previous step's interface
+ * states, the DET predictor and Riemann problems at the Gauss-Legendre times
+ * of eq. (numfluxes) and at tau = dt (the next step's interface data), then the
+ * conservative update.  The step is clipped so that no domain passes t_stop;
+ * domains already at t_stop do not move.  Enqueued on the handle's stream.
+ * dt_out != NULL synchronises the stream and returns the step of domain 0
+ * (latched device errors are returned then). */
 int grprec_step(grprec_handle *h, double t_stop, double *dt_out);
 
-/* Steps until every domain reaches t_end or max_steps steps were taken.  Runs
- * captured HIP graphs of several steps; synchronises between graph chunks.
- * steps_out: steps taken by this call; t_out: time of domain 0. */
+/* Repeated steps of eq. (eq_finite_volume) until every domain reaches t_end
+ * (the last step of each domain is clipped to land on t_end) or max_steps
+ * steps were taken.  Runs captured HIP graphs of several steps; synchronises
+ * between graph chunks.  steps_out, t_out (host, may be NULL): steps taken by
+ * this call and the time of domain 0. */
 int grprec_run(grprec_handle *h, double t_end, int64_t max_steps, int64_t *steps_out,
                double *t_out);
 
 /* Synchronise and report which buffer pair holds the current state
  * (0: q0/v0, 1: q1/v1), the smallest and largest domain time and the number
- * of steps taken since init.  Returns any latched device error. */
+ * of steps taken since init.  Returns any latched device error.  Any output
+ * pointer may be NULL. */
 int grprec_state(grprec_handle *h, int *current, double *t_min, double *t_max, int64_t *steps);
 
-/* Copy the per-domain times (host array of n_segments doubles). */
+/* Synchronise and report the time t^n of the current state (the smallest
+ * domain time, i.e. the time of the state for a single domain) and the number
+ * of steps taken since init (or since the last grprec_set_state).  The cell
+ * averages Q^n and the interface states q_{i+1/2}^{n-1}(dt^{n-1}) of Sec. 3.1
+ * stay in the caller's buffers; grprec_state names the current pair.  Either
+ * pointer may be NULL.  Returns any latched device error. */
+int grprec_get_state(grprec_handle *h, double *t, int64_t *step);
+
+/* Copy the per-domain times t^n (host array of n_segments doubles; each domain
+ * advances with its own dt of eq. dt-FV). */
 int grprec_segment_times(grprec_handle *h, double *t_host);
 
-/* Restart from a saved state: the caller has written the state into the
- * buffers named by `current`; every domain time is set to t, the step counter
- * to steps, and S_max is recomputed.  Clears latched errors. */
+/* Restart from a saved state (checkpoint/resume; not in the paper): the caller
+ * has written the cell averages and interface states into the buffers named
+ * by `current` (0: q0/v0, 1: q1/v1); every domain time is set to t, the step
+ * counter to steps, and S_max (Sec. 4.1) is recomputed from the averages.
+ * Clears latched errors; returns GRPREC_E_NONPHYSICAL if a cell is not a
+ * physical state. */
 int grprec_set_state(grprec_handle *h, int current, double t, int64_t steps);
 
-/* Tile schedule in use, and a way to force one (Euler). */
+/* Tile schedule in use, and a way to force one (Euler; not in the paper: how
+ * the cells of many domains are grouped into workgroups).  set_schedule
+ * rejects schedules and blocks outside the GRPREC_SCHED_* values and
+ * 64/128/256 with GRPREC_E_INVALID. */
 int grprec_get_schedule(grprec_handle *h, int *schedule, int *block);
 int grprec_set_schedule(grprec_handle *h, int schedule, int block);
 
-/* Time each schedule candidate for `steps` steps from the current state (the
- * fastest of three runs) and keep the fastest candidate whose result is
- * bitwise equal to the first candidate's; the state is restored.  Writes
- * per-candidate milliseconds per step into ms_out[n_max] (candidate order:
- * schedules 1..3 x blocks 64,128,256; a single domain tries segment tiles
- * only; negative when the result differed), and the number written into
- * *n_out. */
+/* Autotuner (not in the paper).  Times each schedule candidate for `steps`
+ * steps from the current state (the fastest of three runs) and keeps the
+ * fastest candidate whose result is bitwise equal to the first candidate's;
+ * the state is restored.  Writes per-candidate milliseconds per step into the
+ * host array ms_out[n_max] (candidate order: schedules 1..3 x blocks
+ * 64,128,256; a single domain tries segment tiles only; negative when the
+ * result differed), and the number written into *n_out.  Needs the snapshot
+ * area of a problem created with schedule AUTO (else GRPREC_E_INVALID). */
 int grprec_autotune(grprec_handle *h, int steps, double *ms_out, int n_max, int *n_out);
 
-/* Counters accumulated since init when count_stats is on: Riemann solves,
- * Newton iterations, predictor sweeps, learned guesses used. */
+/* Solver counters (not in the paper) accumulated while counting is on:
+ * Riemann solves (the interaction step of Sec. 2), Newton iterations on the
+ * star pressure, predictor sweeps, cells predicted (owned cells plus halo
+ * recomputations), learned starts taken. */
 typedef struct {
   uint64_t rs_calls, newton_iters, picard_sweeps, cells_predicted, mlp_guesses;
 } grprec_stats;
 int grprec_enable_stats(grprec_handle *h, int on);
 int grprec_get_stats(grprec_handle *h, grprec_stats *out);
 
-/* Message for a status code. */
+/* Static message for a status code ("unknown error" for other values). */
 const char *grprec_error_string(int code);
+/* Release the handle's host-side plans and graphs (NULL is ignored); the
+ * caller's device buffers are untouched. */
 void grprec_destroy(grprec_handle *h);
 
-/* ---- Riemann problems in bulk (exact Euler solver of the step) ----
- * wl, wr: device [n][3] primitive states (rho, u, p); outputs p* and Newton
- * iterations per problem (device, either may be NULL).  guess as above
- * (mlp_params needed for GRPREC_GUESS_MLP; gate < 0 uses the network for
- * every problem).  Problems that fail get p* = NaN and the negative error code
- * in iters. */
+/* ---- Riemann problems in bulk ----
+ * The exact Euler Riemann solver of the interaction step (Sec. 2, Sec. 4.3:
+ * Newton on the star pressure from the pressure functions of the two waves),
+ * applied to n independent problems: wl, wr are device [n][3] primitive
+ * states (rho, u, p); outputs p* and Newton iterations per problem (device,
+ * either may be NULL).  guess as above (mlp_params needed for
+ * GRPREC_GUESS_MLP; gate < 0 uses the network for every problem).  Problems
+ * that fail get p* = NaN and the negative error code in iters.  Enqueued on
+ * hip_stream. */
 int grprec_riemann_batch(const double *wl, const double *wr, int64_t n, double gamma, int guess,
                          const float *mlp_params, double gate, double tol, int max_iter,
                          double *pstar, int *iters, void *hip_stream);
 
 /* ---- learned star-pressure proposal: features, inference, training ----
- * Unnormalised features x[n][6] (float32) of primitive states wl, wr [n][3]
+ * Not in the paper: a start value for the Newton iteration of the exact
+ * Riemann solver.  Newton still runs to the same tolerance, so the solution
+ * is that of the plain method.  All pointers are device pointers; calls are
+ * enqueued on hip_stream; sizes n < 0 or missing pointers give
+ * GRPREC_E_INVALID. */
+
+/* Unnormalised features x[n][6] (float32) of primitive states wl, wr [n][3]
  * and, when pstar != NULL, targets y[n] = ln(p_star / pbar). */
 int grprec_mlp_features(const double *wl, const double *wr, const double *pstar, int64_t n,
                         double gamma, float *x, float *y, void *hip_stream);
 /* y[n] = network(standardise(x)) with params as laid out above. */
 int grprec_mlp_forward(const float *params, const float *x, float *y, int64_t n,
                        void *hip_stream);
-/* Mean-squared-error loss over the batch and its gradient with respect to the
- * GRPREC_MLP_WEIGHTS weights (grad: device float[GRPREC_MLP_WEIGHTS]; loss:
- * device float[1]).  work: device scratch of grprec_mlp_work_bytes(n) bytes. */
+/* Bytes of device workspace that grprec_mlp_backward and grprec_mlp_loss_grad
+ * need for n samples (per-block partial sums; 0 for n < 1). */
 size_t grprec_mlp_work_bytes(int64_t n);
+/* Backward pass: grad[k] = sum_s dy[s] d y_s / d theta_k over the n samples of
+ * x[n][6] for the GRPREC_MLP_WEIGHTS weights theta (the normaliser is not
+ * differentiated); dy[n] is the upstream gradient of the outputs.  grad:
+ * device float[GRPREC_MLP_WEIGHTS], overwritten.  work: device scratch of at
+ * least grprec_mlp_work_bytes(n) bytes; 1 <= n <= 64 * 2^20. */
+int grprec_mlp_backward(const float *params, const float *x, const float *dy, float *grad,
+                        int64_t n, void *work, void *hip_stream);
+/* Mean-squared-error loss (1/n) sum_s (y_s - t_s)^2 over the batch and its
+ * gradient with respect to the GRPREC_MLP_WEIGHTS weights: the backward pass
+ * with dy = 2 (y - t) / n.  grad: device float[GRPREC_MLP_WEIGHTS]; loss:
+ * device float[1] or NULL.  work as for grprec_mlp_backward. */
 int grprec_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t n,
                          float *grad, float *loss, void *work, void *hip_stream);
 /* One Adam update of the weights (the normaliser is left alone); m, v: device
@@ -233,10 +290,12 @@ int grprec_mlp_loss_grad(const float *params, const float *x, const float *y, in
 int grprec_mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr,
                     float beta1, float beta2, float eps, void *hip_stream);
 
-/* Record the Riemann problems solved by the following steps: each interface's
- * first flux problem is written as (rhoL, uL, pL, rhoR, uR, pR, p*) doubles into
- * the device ring [cap][7]; *count_dev (device int64) counts attempts (entries
- * beyond cap are dropped).  ring = NULL switches recording off. */
+/* Record the Riemann problems solved by the following steps (training data for
+ * the learned start; not in the paper): each interface's first flux problem
+ * (the interaction at the first Gauss-Legendre time, Sec. 2) is written as
+ * (rhoL, uL, pL, rhoR, uR, pR, p*) doubles into the device ring [cap][7];
+ * *count_dev (device int64) counts attempts (entries beyond cap are dropped).
+ * ring = NULL switches recording off.  Euler only. */
 int grprec_harvest(grprec_handle *h, double *ring, int64_t cap, int64_t *count_dev);
 
 #ifdef __cplusplus

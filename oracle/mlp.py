@@ -5,9 +5,12 @@ Inputs are standardised with the parameter block's mean/std; the loss is the
 mean squared error over a batch.  Parameter layout (flat): W1[32][6], b1[32],
 W2[32][32], b2[32], W3[32], b3, mean[6], std[6].
 
-The gradient is written out by the chain rule; the parity of that gradient
-is pinned by central differences in the tests.  The network is not from the
-paper, so these functions are "parity unpinned" with respect to it.
+The gradient is written out by the chain rule.  Pins (tests): the forward
+pass against closed forms of single-path parameter blocks (weight layout,
+standardisation, input slots), the features against a hand-computed case and
+their invariances, the gradients against central differences.  The network
+is not from the paper: these pins come from its definition here, not from
+the paper.
 """
 from __future__ import annotations
 
@@ -47,6 +50,25 @@ def forward(P, x):
     h1 = np.tanh(z @ W1.T + b1)
     h2 = np.tanh(h1 @ W2.T + b2)
     return h2 @ W3 + b3
+
+
+def backward(P, x, dy):
+    """Gradient of sum_s dy_s y_s with respect to the 1313 weights, where y_s is
+    the network output for sample s and dy_s the given upstream gradient."""
+    W1, b1, W2, b2, W3, b3, mean, std = unpack(P)
+    z = (np.asarray(x, dtype=np.float64) - mean) / std
+    dy = np.asarray(dy, dtype=np.float64)
+    h1 = np.tanh(z @ W1.T + b1)
+    h2 = np.tanh(h1 @ W2.T + b2)
+    gW3 = h2.T @ dy
+    gb3 = dy.sum()
+    d2 = np.outer(dy, W3) * (1 - h2 * h2)  # upstream gradient at pre-activation 2
+    gW2 = d2.T @ h1
+    gb2 = d2.sum(axis=0)
+    d1 = (d2 @ W2) * (1 - h1 * h1)         # upstream gradient at pre-activation 1
+    gW1 = d1.T @ z
+    gb1 = d1.sum(axis=0)
+    return np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, [gb3]])
 
 
 def loss(P, x, t):

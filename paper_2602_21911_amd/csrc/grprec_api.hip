@@ -373,7 +373,7 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (!(p.picard_tol > 0.0)) p.picard_tol = 1e-13;
   if (p.mlp_gate == 0.0) p.mlp_gate = 0.1;
   if (p.recon != GRPREC_RECON_LINEAR && p.recon != GRPREC_RECON_NL) return GRPREC_E_INVALID;
-  if (p.nl_lambda_c == 0.0) p.nl_lambda_c = 10.0;
+  if (p.nl_lambda_c == 0.0) p.nl_lambda_c = 1e9;
   if (p.nl_eps == 0.0) p.nl_eps = 1e-14;
   // bounds that keep the weights' products of fourth powers inside double range
   if (!(p.nl_lambda_c > 0.0 && p.nl_lambda_c <= 1e30)) return GRPREC_E_INVALID;
@@ -554,6 +554,16 @@ int grprec_state(grprec_handle *h, int *current, double *t_min, double *t_max, i
   if (t_min) *t_min = *std::min_element(t.begin(), t.end());
   if (t_max) *t_max = *std::max_element(t.begin(), t.end());
   return err_code(h->host_ctl->err);
+}
+
+int grprec_get_state(grprec_handle *h, double *t, int64_t *step) {
+  if (!h) return GRPREC_E_INVALID;
+  double tmin = 0.0;
+  int64_t k = 0;
+  const int rc = grprec_state(h, nullptr, &tmin, nullptr, &k);
+  if (t) *t = tmin;
+  if (step) *step = k;
+  return rc;
 }
 
 int grprec_segment_times(grprec_handle *h, double *t_host) {

@@ -82,15 +82,19 @@ __global__ void forward_kernel(const float *P, const float *x, float *y, long lo
   }
 }
 
-// Loss and gradient.  Block of 64 samples (one per thread): forward and
+// Backward pass.  Block of 64 samples (one per thread): forward and
 // backward per sample in registers; the per-sample outer products are then
 // summed over the block from LDS, one group of parameters per thread, and
 // written as this block's partial sums (deterministic, no atomics).
+// LOSS: t holds targets, the upstream gradient is dy = 2 (y - t) / n and the
+// last partial is the block's share of the mean squared error; otherwise t
+// holds dy itself and the last partial is 0.
 constexpr int GB = 64;
 constexpr int NW = GRPREC_MLP_WEIGHTS;
 
-__global__ __launch_bounds__(GB) void loss_grad_partial(const float *P, const float *xin, const float *t,
-                                                        long long n, float inv_n, float *partial) {
+template <bool LOSS>
+__global__ __launch_bounds__(GB) void grad_partial(const float *P, const float *xin, const float *t,
+                                                   long long n, float inv_n, float *partial) {
   __shared__ float sx[6][GB];
   __shared__ float sh1[32][GB];
   __shared__ float sh2[32][GB];
@@ -122,8 +126,8 @@ __global__ __launch_bounds__(GB) void loss_grad_partial(const float *P, const fl
     h2[j] = mlp_tanh(a);
     y = fmaf(W3[j], h2[j], y);
   }
-  const float r = live ? y - t[i] : 0.0f;
-  const float dy = 2.0f * r * inv_n;
+  const float r = (LOSS && live) ? y - t[i] : 0.0f;
+  const float dy = LOSS ? 2.0f * r * inv_n : (live ? t[i] : 0.0f);
   float d2[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) d2[j] = dy * W3[j] * (1.0f - h2[j] * h2[j]);
@@ -195,6 +199,22 @@ __global__ void adam_kernel(float *P, const float *g, float *m, float *v, float 
   P[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
 }
 
+// Both passes of the gradient: per-block partial sums into `partial`
+// (nb x (NW + 1) floats), then their sum over the blocks.
+int gradient(bool with_loss, const float *params, const float *x, const float *t, int64_t n, float *grad,
+             float *loss, float *partial, hipStream_t st) {
+  const int nb = (int)((n + GB - 1) / GB);
+  if (with_loss)
+    hipLaunchKernelGGL(grad_partial<true>, dim3(nb), dim3(GB), 0, st, params, x, t, (long long)n,
+                       1.0f / (float)n, partial);
+  else
+    hipLaunchKernelGGL(grad_partial<false>, dim3(nb), dim3(GB), 0, st, params, x, t, (long long)n, 0.0f,
+                       partial);
+  if (hipGetLastError() != hipSuccess) return GRPREC_E_HIP;
+  hipLaunchKernelGGL(reduce_partials, dim3((NW + 1 + 255) / 256), dim3(256), 0, st, (const float *)partial,
+                     nb, grad, loss);
+  return hipGetLastError() == hipSuccess ? GRPREC_OK : GRPREC_E_HIP;
+}
 }  // namespace
 
 extern "C" {
@@ -236,18 +256,18 @@ size_t grprec_mlp_work_bytes(int64_t n) {
   return sizeof(float) * (size_t)nb * (NW + 1);
 }
 
+int grprec_mlp_backward(const float *params, const float *x, const float *dy, float *grad, int64_t n,
+                        void *work, void *hip_stream) {
+  if (!params || !x || !dy || n < 1 || !grad || !work) return GRPREC_E_INVALID;
+  if (n > (int64_t)GB * 1048576) return GRPREC_E_INVALID;
+  return gradient(false, params, x, dy, n, grad, nullptr, (float *)work, (hipStream_t)hip_stream);
+}
+
 int grprec_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t n, float *grad,
                          float *loss, void *work, void *hip_stream) {
   if (!params || !x || !y || n < 1 || !grad || !work) return GRPREC_E_INVALID;
   if (n > (int64_t)GB * 1048576) return GRPREC_E_INVALID;
-  const int nb = (int)((n + GB - 1) / GB);
-  hipStream_t st = (hipStream_t)hip_stream;
-  hipLaunchKernelGGL(loss_grad_partial, dim3(nb), dim3(GB), 0, st, params, x, y, (long long)n,
-                     1.0f / (float)n, (float *)work);
-  if (hipGetLastError() != hipSuccess) return GRPREC_E_HIP;
-  hipLaunchKernelGGL(reduce_partials, dim3((NW + 1 + 255) / 256), dim3(256), 0, st, (const float *)work, nb,
-                     grad, loss);
-  return hipGetLastError() == hipSuccess ? GRPREC_OK : GRPREC_E_HIP;
+  return gradient(true, params, x, y, n, grad, loss, (float *)work, (hipStream_t)hip_stream);
 }
 
 int grprec_mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, float beta1,

@@ -39,10 +39,12 @@ GRPREC_MLP_NPARAMS = 1325
 
 EXPORTED = [
     "grprec_workspace_bytes", "grprec_init", "grprec_step", "grprec_run", "grprec_state",
+    "grprec_get_state",
     "grprec_segment_times", "grprec_set_state", "grprec_get_schedule", "grprec_set_schedule",
     "grprec_autotune", "grprec_enable_stats", "grprec_get_stats", "grprec_error_string",
     "grprec_destroy", "grprec_riemann_batch", "grprec_mlp_features", "grprec_mlp_forward",
-    "grprec_mlp_work_bytes", "grprec_mlp_loss_grad", "grprec_mlp_adam", "grprec_harvest",
+    "grprec_mlp_work_bytes", "grprec_mlp_backward", "grprec_mlp_loss_grad", "grprec_mlp_adam",
+    "grprec_harvest",
 ]
 
 _vp = ctypes.c_void_p
@@ -97,6 +99,7 @@ def lib():
         L.grprec_step.argtypes = [_vp, ctypes.c_double, _dp]
         L.grprec_run.argtypes = [_vp, ctypes.c_double, ctypes.c_int64, _i64p, _dp]
         L.grprec_state.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), _dp, _dp, _i64p]
+        L.grprec_get_state.argtypes = [_vp, _dp, _i64p]
         L.grprec_segment_times.argtypes = [_vp, _dp]
         L.grprec_set_state.argtypes = [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64]
         L.grprec_get_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int),
@@ -118,6 +121,7 @@ def lib():
         L.grprec_mlp_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
         L.grprec_mlp_work_bytes.argtypes = [ctypes.c_int64]
         L.grprec_mlp_work_bytes.restype = ctypes.c_size_t
+        L.grprec_mlp_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp]
         L.grprec_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.grprec_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]
@@ -176,6 +180,14 @@ def grprec_state(h: int):
     _chk(lib().grprec_state(h, ctypes.byref(cur), ctypes.byref(tmin), ctypes.byref(tmax),
                             ctypes.byref(steps)), "grprec_state")
     return cur.value, tmin.value, tmax.value, steps.value
+
+
+def grprec_get_state(h: int):
+    """(time of the current state, steps since init)."""
+    t = ctypes.c_double(0)
+    steps = ctypes.c_int64(0)
+    _chk(lib().grprec_get_state(h, ctypes.byref(t), ctypes.byref(steps)), "grprec_get_state")
+    return t.value, steps.value
 
 
 def grprec_segment_times(h: int, n_segments: int) -> np.ndarray:
@@ -266,6 +278,11 @@ def grprec_mlp_work_bytes(n: int) -> int:
     return lib().grprec_mlp_work_bytes(n)
 
 
+def grprec_mlp_backward(params, x, dy, grad, work, stream=None):
+    _chk(lib().grprec_mlp_backward(_ptr(params), _ptr(x), _ptr(dy), _ptr(grad), x.shape[0], _ptr(work),
+                                   _stream(stream)), "grprec_mlp_backward")
+
+
 def grprec_mlp_loss_grad(params, x, y, grad, loss, work, stream=None):
     _chk(lib().grprec_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _ptr(grad),
                                     _ptr(loss), _ptr(work), _stream(stream)), "grprec_mlp_loss_grad")
@@ -297,7 +314,7 @@ class Simulation:
                  mlp_gate: float = 0.1, warm_start: int = 0, schedule: int = GRPREC_SCHED_AUTO,
                  block: int = 0, max_newton: int = 50, newton_tol: float = 1e-12,
                  max_picard: int = 64, picard_tol: float = 1e-13, recon: int = GRPREC_RECON_LINEAR,
-                 nl_lambda_c: float = 10.0, nl_eps: float = 1e-14, datum: int = GRPREC_DATUM_EXACT,
+                 nl_lambda_c: float = 1e9, nl_eps: float = 1e-14, datum: int = GRPREC_DATUM_EXACT,
                  device: str = "cuda"):
         import torch
         self.torch = torch

@@ -163,21 +163,22 @@ def test_network_full_size_learned_start(G):
 
 @pytest.mark.parametrize("datum", [0, 1])
 def test_tube_network_full_size(G, datum):
-    """The benchmark's tube network (10^4 shock tubes, GRPrecNL order 3,
-    autotuned schedule), exact or two-rarefaction datum: sampled tubes after
-    5 steps equal the oracle."""
+    """The benchmark's tube network (10^4 shock tubes, GRPrecNL order 3 with
+    lambda_C = 10, autotuned schedule), exact or two-rarefaction datum:
+    sampled tubes after 5 steps equal the oracle."""
     net = I.tube_network(n_seg=10000, seed=I.SEED_TUBE_NETWORK)
     steps = 5
     sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
                        bc=G.GRPREC_BC_TRANSMISSIVE, recon=G.GRPREC_RECON_NL, datum=datum,
-                       schedule=G.GRPREC_SCHED_AUTO)
+                       nl_lambda_c=oracle.LAMBDA_C_TABLE, schedule=G.GRPREC_SCHED_AUTO)
     try:
         done, _ = sim.run(1e9, steps)
         assert done == steps
         qg, vg, _, _ = sim.numpy_state()
     finally:
         sim.close()
-    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR, datum=datum)
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR, datum=datum,
+                   nl_lambda_c=oracle.LAMBDA_C_TABLE)
     rng = np.random.default_rng(8 + datum)
     for s in sorted(set(rng.choice(len(net.n_cells), 40, replace=False).tolist())):
         c0, c1 = int(net.cell_off[s]), int(net.cell_off[s + 1])

@@ -55,11 +55,12 @@ def test_trrs_shock_tube_parity(G, order, ratio):
     n = 100
     dx, q, vl, vr = I.euler_shock_tube(n, left=(1.0, 0.0, 1.0), right=(ratio, 0.0, ratio))
     c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
-                   datum=oracle.DATUM_TRRS)
+                   datum=oracle.DATUM_TRRS, nl_lambda_c=oracle.LAMBDA_C_TABLE)
     v = oracle.init_interfaces(c, vl, vr)
     sim = G.Simulation(G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_TRANSMISSIVE,
                        recon=G.GRPREC_RECON_NL, datum=G.GRPREC_DATUM_TRRS,
-                       schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=64)
+                       nl_lambda_c=oracle.LAMBDA_C_TABLE, schedule=G.GRPREC_SCHED_SEGMENT_TILES,
+                       block=64)
     try:
         print(f"TRRS shock tube order {order} ratio {ratio}", flush=True)
         sim.run(0.2)
@@ -75,12 +76,13 @@ def test_trrs_tube_network_parity(G):
     net = I.tube_network(n_seg=60)
     S = len(net.n_cells)
     c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
-                   datum=oracle.DATUM_TRRS)
+                   datum=oracle.DATUM_TRRS, nl_lambda_c=oracle.LAMBDA_C_TABLE)
     v0 = oracle.init_interfaces(c, net.vl, net.vr)
     qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 12)
     sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
                        bc=G.GRPREC_BC_TRANSMISSIVE, recon=G.GRPREC_RECON_NL,
-                       datum=G.GRPREC_DATUM_TRRS, schedule=G.GRPREC_SCHED_PACKED, block=128)
+                       datum=G.GRPREC_DATUM_TRRS, nl_lambda_c=oracle.LAMBDA_C_TABLE,
+                       schedule=G.GRPREC_SCHED_PACKED, block=128)
     try:
         print("TRRS tube network", flush=True)
         steps, _ = sim.run(1e9, 12)

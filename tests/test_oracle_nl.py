@@ -199,12 +199,13 @@ def test_paper_grprecnl_advection_table():
 def test_square_wave_order_two_without_oscillations():
     """Sec. 4.2.2: GRPrecNL removes the order-2 over- and undershoots that
     GRPrec shows at the square wave's jumps; at higher orders it only reduces
-    them."""
+    them.  This holds with lambda_C = 10; with the printed 1e9 the centred
+    polynomial keeps the order-2 overshoot (the reading of lambda_C)."""
     dx, q, vl, vr = I.adv_square(64)
     out = {}
     for order in (2, 3, 4, 5):
         for recon in (oracle.LINEAR, oracle.NONLINEAR):
-            c = oracle.cfg(oracle.ADVECTION, order, recon=recon)
+            c = oracle.cfg(oracle.ADVECTION, order, recon=recon, nl_lambda_c=oracle.LAMBDA_C_TABLE)
             v = oracle.init_interfaces(c, vl, vr)
             qn, _, _, _, _ = oracle.run(c, dx, q, v, 0.0, 1.0)
             out[order, recon] = max(qn.max() - 1.0, -qn.min())
@@ -213,6 +214,9 @@ def test_square_wave_order_two_without_oscillations():
     assert out[2, oracle.NONLINEAR] < 1e-5
     for order in (3, 4, 5):
         assert out[order, oracle.NONLINEAR] < 0.8 * out[order, oracle.LINEAR], order
+    c = oracle.cfg(oracle.ADVECTION, 2, recon=oracle.NONLINEAR, nl_lambda_c=oracle.LAMBDA_C_PRINTED)
+    qn, _, _, _, _ = oracle.run(c, dx, q, oracle.init_interfaces(c, vl, vr), 0.0, 1.0)
+    assert max(qn.max() - 1.0, -qn.min()) > 0.1
 
 
 def test_eigenvectors_of_the_flux_jacobian():
@@ -294,7 +298,8 @@ def test_sod_with_grprecnl_under_these_readings():
     figure is therefore not reproduced; both sides must report the failure."""
     dx, q, vl, vr = I.euler_shock_tube(100)
     for order in (2, 3, 4):
-        c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR)
+        c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
+                       nl_lambda_c=oracle.LAMBDA_C_TABLE)
         v = oracle.init_interfaces(c, vl, vr)
         if order == 2:
             qn, vn, _, _, _ = oracle.step(c, dx, q, v, 0.0, 0.2)  # the first step passes

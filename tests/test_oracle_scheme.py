@@ -312,9 +312,10 @@ def test_trrs_datum_shock_tube_runs_and_differs():
     """On a shock tube the datum changes the scheme (the datum at the shock is
     approximate) but the solution stays close to the exact-datum one."""
     dx, q, vl, vr = I.euler_shock_tube(100, left=(1.0, 0.0, 1.0), right=(0.5, 0.0, 0.5))
-    ce = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR)
+    ce = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
+                    nl_lambda_c=oracle.LAMBDA_C_TABLE)
     ct = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
-                    datum=oracle.DATUM_TRRS)
+                    datum=oracle.DATUM_TRRS, nl_lambda_c=oracle.LAMBDA_C_TABLE)
     qe, _, _, _, _ = oracle.run(ce, dx, q, oracle.init_interfaces(ce, vl, vr), 0.0, 0.2)
     qt, _, _, _, _ = oracle.run(ct, dx, q, oracle.init_interfaces(ct, vl, vr), 0.0, 0.2)
     d = np.abs(qt - qe).max()
@@ -337,3 +338,65 @@ def test_nonphysical_cell_is_reported_wherever_it_sits():
         with pytest.raises(oracle.OracleError) as ei:
             oracle.step(c, dx, qb, v, 0.0, 1.0)
         assert ei.value.code == oracle.E_NONPHYSICAL
+
+
+def _mixed_sign_states(rng, n):
+    """Euler cell averages whose fastest wave runs left: velocities of both
+    signs, the largest |u| + c at a cell with u < 0, and the largest |u| and
+    the largest c in different cells (so max|u| + max c is not the answer)."""
+    rho = rng.uniform(0.5, 2.0, n)
+    u = rng.uniform(-0.5, 0.5, n)
+    p = rng.uniform(0.5, 1.5, n)
+    k = n // 3
+    u[k], rho[k], p[k] = -2.5, 1.0, 1.0           # fastest: |u| + c = 2.5 + sqrt(1.4)
+    u[k + 1], rho[k + 1], p[k + 1] = 2.0, 1.0, 1.0  # fastest rightward one is slower
+    u[k + 2], rho[k + 2], p[k + 2] = 0.0, 0.5, 3.0  # largest c = sqrt(8.4), |u| = 0
+    return rho, u, p
+
+
+def test_smax_value_with_leftward_and_mixed_velocities():
+    """Sec. 4.1: S_max = max_i max_j |lambda_j(Q_i)| = max_i (|u_i| + c_i).  The
+    data put the maximum at a leftward-moving cell and the largest |u| and
+    largest c in different cells, so max(u + c), max|u| + max c or a missing
+    absolute value all give other numbers."""
+    rng = np.random.default_rng(31)
+    n = 40
+    rho, u, p = _mixed_sign_states(rng, n)
+    q = I.prim_to_cons(rho, u, p)
+    c = oracle.cfg(oracle.EULER, 3)
+    want = np.max(np.abs(u) + np.sqrt(1.4 * p / rho))
+    got = oracle.smax(c, q)
+    assert abs(got - want) <= 1e-15 * want
+    assert want > np.max(u + np.sqrt(1.4 * p / rho)) + 0.1
+    assert want < np.max(np.abs(u)) + np.max(np.sqrt(1.4 * p / rho)) - 0.1
+    # whole-domain reversal u -> -u leaves S_max unchanged
+    assert oracle.smax(c, I.prim_to_cons(rho, -u, p)) == got
+
+
+def test_smax_per_segment_sets_each_segments_step():
+    """Segments advance with their own dt = C_CFL dx_s / S_max,s (eq. dt-FV):
+    after one unclipped step each segment's time is that dt, with S_max of its
+    own cells only.  Smooth data whose velocity is mostly negative in every
+    other segment, so the largest |u| + c sits at a leftward flow there."""
+    sizes = [17, 9, 30, 12]
+    lengths = [0.5, 0.2, 1.3, 0.7]
+    qs, vs, want = [], [], []
+    for s, n in enumerate(sizes):
+        xm = (np.arange(n) + 0.5) / n
+        xf = np.arange(n + 1) / n
+        sgn = -1.0 if s % 2 else 1.0
+
+        def prim(x):
+            return (1.0 + 0.2 * np.sin(2 * np.pi * x), sgn * (1.0 + 0.5 * np.cos(2 * np.pi * x)) * (0.5 + s),
+                    1.0 + 0.1 * np.cos(2 * np.pi * x))
+        rho, u, p = prim(xm)
+        qs.append(I.prim_to_cons(rho, u, p))      # point values stand in for averages
+        vs.append(I.prim_to_cons(*prim(xf)))
+        want.append(0.9 * (lengths[s] / n) / np.max(np.abs(u) + np.sqrt(1.4 * p / rho)))
+    cell_off = np.concatenate([[0], np.cumsum(sizes)])
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    q = np.ascontiguousarray(np.concatenate(qs, axis=1))
+    v = np.ascontiguousarray(np.concatenate(vs, axis=1))
+    dx = np.array(lengths) / np.array(sizes)
+    _, _, t, _ = oracle.run_segments(c, cell_off, dx, q, v, np.zeros(len(sizes)), 1e9, 1)
+    np.testing.assert_allclose(t, want, rtol=1e-14)
