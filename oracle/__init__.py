@@ -26,6 +26,7 @@ DATUM_EXACT, DATUM_TRRS = 0, 1    # Euler interface datum solver (Sec. 4.1)
 # GRPrecNL weight of the centred polynomial, eq. (omega): the value Sec. 3.3
 # prints, and the value with which the printed GRPrecNL advection results of
 # Sec. 4.2.3 are reproduced (the reading of the two documented with the tests).
+SOURCE_NONE, SOURCE_LINEAR = 0, 1  # S(Q) = 0 or -kappa Q
 LAMBDA_C_PRINTED = 1e9
 LAMBDA_C_TABLE = 10.0
 
@@ -47,7 +48,8 @@ class Cfg(ctypes.Structure):
                 ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int),
                 ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
                 ("recon", ctypes.c_int), ("nl_lambda_c", ctypes.c_double),
-                ("nl_eps", ctypes.c_double), ("nl_r", ctypes.c_double), ("datum", ctypes.c_int)]
+                ("nl_eps", ctypes.c_double), ("nl_r", ctypes.c_double), ("datum", ctypes.c_int),
+                ("source", ctypes.c_int), ("kappa", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -104,13 +106,16 @@ def _p(a: np.ndarray):
 
 def cfg(system=ADVECTION, order=3, cfl=0.9, lam=1.0, gamma=1.4, bc=PERIODIC, newton_tol=1e-12,
         newton_max=50, picard_tol=1e-13, picard_max=64, recon=LINEAR,
-        nl_lambda_c=LAMBDA_C_PRINTED, nl_eps=1e-14, nl_r=4.0, datum=DATUM_EXACT) -> Cfg:
+        nl_lambda_c=LAMBDA_C_PRINTED, nl_eps=1e-14, nl_r=4.0, datum=DATUM_EXACT, source=SOURCE_NONE,
+        kappa=0.0) -> Cfg:
     """GRPrecNL weights: r, eps and lambda_C = 1e9 as printed (Sec. 3.3).  With
     1e9 GRPrecNL coincides with GRPrec on smooth data; the paper's GRPrecNL
     results (Sec. 4.2.3 table, Sec. 4.2.2 square wave) are reproduced with
-    lambda_C = 10 (pass nl_lambda_c=LAMBDA_C_TABLE)."""
+    lambda_C = 10 (pass nl_lambda_c=LAMBDA_C_TABLE).  source=SOURCE_LINEAR adds
+    S(Q) = -kappa Q to eq. (eq_hyperbolic_system) (eqs. eq_finite_volume and
+    source)."""
     return Cfg(system, order - 1, cfl, lam, gamma, bc, bc, newton_tol, newton_max, picard_tol,
-               picard_max, recon, nl_lambda_c, nl_eps, nl_r, datum)
+               picard_max, recon, nl_lambda_c, nl_eps, nl_r, datum, source, kappa)
 
 
 class OracleError(RuntimeError):

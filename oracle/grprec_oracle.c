@@ -24,7 +24,11 @@
  *     exact solver or, for the Euler equations, optionally from the
  *     two-rarefaction approximation (Sec. 4.1);
  *   - time step from eq. (dt-FV) with S_max as in Sec. 4.1;
- *   - conservative one-step update, eq. (eq_finite_volume), without source.
+ *   - conservative one-step update, eq. (eq_finite_volume), optionally with the
+ *     linear relaxation source S(Q) = -kappa Q: the predictor treats it
+ *     implicitly (locally implicit space-time DG, Sec. 2) and the source
+ *     integral of eq. (source) is the Gauss-Legendre quadrature of S over the
+ *     cell's space-time polynomial.
  * The paper gives no details of the DET predictor, of the exact Euler Riemann
  * solver or of the first-step interface data; the readings used are stated at
  * each function.  Precision: IEEE double throughout.
@@ -60,6 +64,8 @@ typedef struct {
   double nl_eps;      /* GRPrecNL epsilon (1e-14) */
   double nl_r;        /* GRPrecNL exponent r (4) */
   int datum;          /* Euler interface datum: 0 = exact Riemann solver, 1 = two-rarefaction */
+  int source;         /* 0 = none, 1 = linear relaxation S(Q) = -kappa Q (every component) */
+  double kappa;       /* relaxation rate of source 1, >= 0 */
 } orc_cfg;
 
 typedef struct {
@@ -690,18 +696,24 @@ static int orc_interact(const orc_cfg *cf, const double *QL, const double *QR, d
  *   K[b][l] = l_b(1) l_l(1) - int_0^1 l_b'(t) l_l(t) dt,  D[a][k] = l_k'(g_a).
  * Solved by Picard iteration from q = w (constant in time):
  *   q <- K^{-1} l(0) w_a - nu K^{-1} diag(w) (D F(q)),
- * until max|change| <= picard_tol (1 + max|q|), at most picard_max sweeps. */
+ * until max|change| <= picard_tol (1 + max|q|), at most picard_max sweeps.
+ * With the source S(q) = -kappa q of eq. (GRP) the weak form gains the nodal
+ * source term dt w_b S(q[a][b]) on the right.  It is taken implicitly (the
+ * predictor is locally implicit, Sec. 2, which is what admits stiff sources):
+ * with z = kappa dt it moves to the left as z diag(w), so the same iteration
+ * runs with K replaced by K_z = K + z diag(w); only the flux term is iterated. */
 
 typedef struct {
   int n;
   double g[MAXN], w[MAXN];
   double D[MAXN][MAXN];
-  double Kinv_l0[MAXN];        /* K^{-1} l(0) */
-  double KinvW[MAXN][MAXN];    /* K^{-1} diag(w) */
+  double Kinv_l0[MAXN];        /* K_z^{-1} l(0) */
+  double KinvW[MAXN][MAXN];    /* K_z^{-1} diag(w) */
   double l0[MAXN], l1[MAXN];   /* l_a(0), l_a(1) */
 } orc_st;
 
-static int orc_st_init(int m, orc_st *s) {
+/* z = kappa dt of the implicit source (0 without source). */
+static int orc_st_init(int m, double z, orc_st *s) {
   int n = m + 1;
   s->n = n;
   orc_gauss_legendre(n, s->g, s->w);
@@ -712,6 +724,7 @@ static int orc_st_init(int m, orc_st *s) {
       for (int qn = 0; qn < n; ++qn)
         integral += s->w[qn] * orc_lagr_d(n, s->g, b, s->g[qn]) * orc_lagr(n, s->g, l, s->g[qn]);
       K[b * n + l] = orc_lagr(n, s->g, b, 1.0) * orc_lagr(n, s->g, l, 1.0) - integral;
+      if (b == l) K[b * n + l] += z * s->w[b];
       I[b * n + l] = (b == l) ? 1.0 : 0.0;
     }
   }
@@ -811,7 +824,7 @@ int orc_predictor_cell(const orc_cfg *cf, double nu, const double *w, double *q,
                        int *iters) {
   orc_st s;
   if (cf->m < 1 || cf->m > 4) return ORC_E_INVALID;
-  orc_st_init(cf->m, &s);
+  orc_st_init(cf->m, 0.0, &s);
   int rc = orc_predict(cf, &s, nu, w, q, iters);
   orc_traces(cf, &s, q, TL, TR);
   return rc;
@@ -822,7 +835,7 @@ int orc_predictor_cell(const orc_cfg *cf, double nu, const double *w, double *q,
 int orc_predictor_matrices(int m, double *g, double *w, double *D, double *Kinv_l0, double *KinvW) {
   orc_st s;
   if (m < 1 || m > 4) return ORC_E_INVALID;
-  orc_st_init(m, &s);
+  orc_st_init(m, 0.0, &s);
   int n = m + 1;
   for (int a = 0; a < n; ++a) {
     g[a] = s.g[a];
@@ -888,25 +901,29 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
                      orc_stats *st) {
   if (n < 1 || cf->m < 1 || cf->m > 4 || cf->recon < 0 || cf->recon > 1) return ORC_E_INVALID;
   if (cf->datum < 0 || cf->datum > 1) return ORC_E_INVALID;
+  if (cf->source < 0 || cf->source > 1 || !(cf->kappa >= 0.0)) return ORC_E_INVALID;
   int m = cf->m, nv = orc_nvar(cf), nn = m + 1;
   int per = (cf->bc_left == 0);
   double R[5 * 5];
   orc_recon_matrix(m, R);
   orc_nl nlt;
   if (cf->recon == 1) orc_nl_init(m, &nlt);
-  orc_st s;
-  orc_st_init(m, &s);
 
   double S = orc_smax(cf, n, q);
   if (!(S > 0.0) || !isfinite(S)) return ORC_E_NONPHYSICAL;
   double dt, tn;
   orc_dt(cf->cfl, dx, S, t, t_end, &dt, &tn);
   double nu = dt / dx;
+  /* predictor matrices with the implicit source of this step, z = kappa dt */
+  const double kap = cf->source == 1 ? cf->kappa : 0.0;
+  orc_st s;
+  orc_st_init(m, kap * dt, &s);
 
   int ntr = nv * (nn + 1);
   double *TL = (double *)malloc(sizeof(double) * ntr * n);
   double *TR = (double *)malloc(sizeof(double) * ntr * n);
   double *Fb = (double *)malloc(sizeof(double) * nv * (n + 1));
+  double *Si = (double *)malloc(sizeof(double) * nv * n); /* S^n_i of eq. (source) */
   int rc = ORC_OK;
 
   for (int i = 0; i < n && rc == ORC_OK; ++i) {
@@ -956,18 +973,31 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
       if (it > st->picard_max_seen) st->picard_max_seen = it;
     }
     orc_traces(cf, &s, qh, TL + (size_t)ntr * i, TR + (size_t)ntr * i);
+    /* eq. (source): the space-time mean of S over the cell, by the tensor
+     * Gauss-Legendre rule on the predictor's nodes (exact for S linear) */
+    for (int vv = 0; vv < nv; ++vv) {
+      double acc = 0.0;
+      for (int a = 0; a < nn; ++a)
+        for (int b = 0; b < nn; ++b) acc += s.w[a] * s.w[b] * (-kap * qh[(vv * nn + a) * nn + b]);
+      Si[vv * n + i] = acc;
+    }
   }
 
   /* Transmissive ends: a ghost cell outside each end holds the end cell's
-   * average as constant data (zero-gradient extrapolation); a constant state
-   * is its own space-time evolution, so its trace is that average at every
-   * time. */
+   * average as constant data (zero-gradient extrapolation).  Constant data
+   * have no flux gradient, so the predictor only applies the source: the
+   * solution at the time nodes is (K_z^{-1} l(0))_b times the average, and
+   * l(1) . K_z^{-1} l(0) times it at the end of the step (without source a
+   * constant state is its own evolution). */
   double *GL = (double *)malloc(sizeof(double) * ntr);
   double *GR = (double *)malloc(sizeof(double) * ntr);
+  double gend = 0.0;
+  for (int b = 0; b < nn; ++b) gend += s.l1[b] * s.Kinv_l0[b];
   for (int vv = 0; vv < nv; ++vv)
     for (int b = 0; b <= nn; ++b) {
-      GL[vv * (nn + 1) + b] = q[vv * n + 0];
-      GR[vv * (nn + 1) + b] = q[vv * n + n - 1];
+      const double fac = kap == 0.0 ? 1.0 : (b < nn ? s.Kinv_l0[b] : gend);
+      GL[vv * (nn + 1) + b] = fac * q[vv * n + 0];
+      GR[vv * (nn + 1) + b] = fac * q[vv * n + n - 1];
     }
 
   /* interfaces k = 0..n; interface k lies between cells k-1 and k */
@@ -1012,7 +1042,8 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
     for (int i = 0; i < n; ++i) {
       double Q[3];
       for (int vv = 0; vv < nv; ++vv) {
-        q_out[vv * n + i] = q[vv * n + i] - nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]);
+        q_out[vv * n + i] =
+            q[vv * n + i] - nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]) + dt * Si[vv * n + i];
         Q[vv] = q_out[vv * n + i];
       }
       if (orc_check_state(cf, Q) != ORC_OK) rc = ORC_E_NONPHYSICAL;
@@ -1021,6 +1052,7 @@ int orc_segment_step(const orc_cfg *cf, int n, double dx, const double *q, const
   free(TL);
   free(TR);
   free(Fb);
+  free(Si);
   free(GL);
   free(GR);
   if (dt_out) *dt_out = dt;
