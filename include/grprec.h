@@ -279,6 +279,17 @@ size_t grprec_mlp_work_bytes(int64_t n);
  * least grprec_mlp_work_bytes(n) bytes; 1 <= n <= 64 * 2^20. */
 int grprec_mlp_backward(const float *params, const float *x, const float *dy, float *grad,
                         int64_t n, void *work, void *hip_stream);
+/* grprec_mlp_backward without caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the per-block partial sums live in a
+ * fixed device array of the library (5.1 MiB per device, kept until the
+ * process ends), so at most GRPREC_MLP_NOALLOC_MAX samples per call
+ * (1 <= n <= 65536, else GRPREC_E_INVALID).  Same kernels and same result as
+ * grprec_mlp_backward.  Every call on a device shares that device's array:
+ * calls that overlap on one device (several streams or threads) race. */
+#define GRPREC_MLP_NOALLOC_MAX 65536
+int grprec_mlp_backward_noalloc(const float *params, const float *x, const float *dy, float *grad,
+                                int64_t n, void *hip_stream);
 /* Mean-squared-error loss (1/n) sum_s (y_s - t_s)^2 over the batch and its
  * gradient with respect to the GRPREC_MLP_WEIGHTS weights: the backward pass
  * with dy = 2 (y - t) / n.  grad: device float[GRPREC_MLP_WEIGHTS]; loss:

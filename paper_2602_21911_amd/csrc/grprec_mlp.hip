@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/grprec.h"
 #include "grprec_device.h"
@@ -215,6 +216,35 @@ int gradient(bool with_loss, const float *params, const float *x, const float *t
                      nb, grad, loss);
   return hipGetLastError() == hipSuccess ? GRPREC_OK : GRPREC_E_HIP;
 }
+// Partial sums of grprec_mlp_backward_noalloc, in a fixed device array
+// instead of caller workspace: room for kNoAllocBlocks blocks of GB samples
+// (5.1 MiB, held on every device the library runs on until the process ends).
+// Host code never passes the array's name to a kernel: the name is a host-side
+// stand-in, and each device's copy has its own address, looked up once per
+// device with hipGetSymbolAddress.
+constexpr int kNoAllocBlocks = 1024;
+__device__ __align__(256) float scratch[(size_t)kNoAllocBlocks * (NW + 1)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with it current).
+int scratch_of_current_device(float **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GRPREC_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return GRPREC_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GRPREC_E_HIP;
+    g_scratch[dev] = (float *)p;
+  }
+  *out = g_scratch[dev];
+  return GRPREC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -261,6 +291,16 @@ int grprec_mlp_backward(const float *params, const float *x, const float *dy, fl
   if (!params || !x || !dy || n < 1 || !grad || !work) return GRPREC_E_INVALID;
   if (n > (int64_t)GB * 1048576) return GRPREC_E_INVALID;
   return gradient(false, params, x, dy, n, grad, nullptr, (float *)work, (hipStream_t)hip_stream);
+}
+
+int grprec_mlp_backward_noalloc(const float *params, const float *x, const float *dy, float *grad, int64_t n,
+                                void *hip_stream) {
+  if (!params || !x || !dy || n < 1 || !grad) return GRPREC_E_INVALID;
+  if (n > (int64_t)GB * kNoAllocBlocks) return GRPREC_E_INVALID;
+  float *partial = nullptr;
+  const int rc = scratch_of_current_device(&partial);
+  if (rc != GRPREC_OK) return rc;
+  return gradient(false, params, x, dy, n, grad, nullptr, partial, (hipStream_t)hip_stream);
 }
 
 int grprec_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t n, float *grad,

@@ -36,6 +36,7 @@ GRPREC_RECON_LINEAR, GRPREC_RECON_NL = 0, 1
 GRPREC_DATUM_EXACT, GRPREC_DATUM_TRRS = 0, 1
 GRPREC_MLP_WEIGHTS = 1313
 GRPREC_MLP_NPARAMS = 1325
+GRPREC_MLP_NOALLOC_MAX = 65536
 
 EXPORTED = [
     "grprec_workspace_bytes", "grprec_init", "grprec_step", "grprec_run", "grprec_state",
@@ -43,7 +44,8 @@ EXPORTED = [
     "grprec_segment_times", "grprec_set_state", "grprec_get_schedule", "grprec_set_schedule",
     "grprec_autotune", "grprec_enable_stats", "grprec_get_stats", "grprec_error_string",
     "grprec_destroy", "grprec_riemann_batch", "grprec_mlp_features", "grprec_mlp_forward",
-    "grprec_mlp_work_bytes", "grprec_mlp_backward", "grprec_mlp_loss_grad", "grprec_mlp_adam",
+    "grprec_mlp_work_bytes", "grprec_mlp_backward", "grprec_mlp_backward_noalloc",
+    "grprec_mlp_loss_grad", "grprec_mlp_adam",
     "grprec_harvest",
 ]
 
@@ -122,6 +124,7 @@ def lib():
         L.grprec_mlp_work_bytes.argtypes = [ctypes.c_int64]
         L.grprec_mlp_work_bytes.restype = ctypes.c_size_t
         L.grprec_mlp_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp]
+        L.grprec_mlp_backward_noalloc.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]
         L.grprec_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.grprec_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]
@@ -281,6 +284,11 @@ def grprec_mlp_work_bytes(n: int) -> int:
 def grprec_mlp_backward(params, x, dy, grad, work, stream=None):
     _chk(lib().grprec_mlp_backward(_ptr(params), _ptr(x), _ptr(dy), _ptr(grad), x.shape[0], _ptr(work),
                                    _stream(stream)), "grprec_mlp_backward")
+
+
+def grprec_mlp_backward_noalloc(params, x, dy, grad, stream=None):
+    _chk(lib().grprec_mlp_backward_noalloc(_ptr(params), _ptr(x), _ptr(dy), _ptr(grad), x.shape[0],
+                                           _stream(stream)), "grprec_mlp_backward_noalloc")
 
 
 def grprec_mlp_loss_grad(params, x, y, grad, loss, work, stream=None):
