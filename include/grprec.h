@@ -5,7 +5,7 @@
  * Method (Montecinos, Toro & Mueller, "A generalized Riemann problem-based
  * compact reconstruction method for finite volume schemes"):
  *   one step of the fully discrete ADER finite-volume scheme, eq. (eq_finite_volume)
- *   of Sec. 2 without source, with
+ *   of Sec. 2, without source or with a linear relaxation source, with
  *   - time step dt = C_CFL dx / S_max, eq. (dt-FV), S_max as in Sec. 4.1;
  *   - GRPrec reconstruction of degree m = order-1 from the cell averages
  *     q_{i-1}, q_i, q_{i+1} and the previous step's GRP interface states
@@ -76,6 +76,14 @@ enum {
   GRPREC_DATUM_TRRS = 1   /* two-rarefaction approximation (Sec. 4.1): closed form, no
                              iteration; also used for the first-step data */
 };
+/* Source term S(Q) of eq. (eq_hyperbolic_system). */
+enum {
+  GRPREC_SOURCE_NONE = 0,
+  GRPREC_SOURCE_LINEAR = 1 /* S(Q) = -kappa Q, every component: taken implicitly in the
+                              space-time predictor (the locally implicit DET of Sec. 2,
+                              which admits stiff sources), and dt S^n_i of eq. (source) from
+                              the predicted space-time polynomial in eq. (eq_finite_volume) */
+};
 /* How cells are grouped into workgroup tiles (Euler). */
 enum {
   GRPREC_SCHED_AUTO = 0,          /* autotune at init over the others */
@@ -133,6 +141,9 @@ typedef struct {
                           advection results (Sec. 4.2.3) are reproduced with 10 */
   double nl_eps;       /* GRPrecNL epsilon, [1e-30, 1] (default 1e-14 when 0) */
   int datum;           /* GRPREC_DATUM_* (Euler only) */
+  int source;          /* GRPREC_SOURCE_*; for the Euler equations only with GRPrec and the
+                          exact datum (else GRPREC_E_UNSUPPORTED) */
+  double source_kappa; /* kappa >= 0 of GRPREC_SOURCE_LINEAR */
 } grprec_problem;
 
 typedef struct {

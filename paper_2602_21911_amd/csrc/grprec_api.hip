@@ -30,7 +30,7 @@ hipError_t launch_digest(const double *, long long, Ctl *, hipStream_t);
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t ctl, cell_off, dx, t, smax, tiles, snap, total;
+  size_t ctl, cell_off, dx, t, smax, tiles, src, snap, total;
   long long max_tiles;
   long long snap_doubles;
 };
@@ -67,6 +67,7 @@ static Layout layout(const grprec_problem *p, long long tc) {
   L.smax = o; o = align256(o + sizeof(unsigned long long) * 3 * S);
   L.max_tiles = (p->system == GRPREC_EULER) ? tc / 62 + S + 2 : 0;
   L.tiles = o; o = align256(o + sizeof(Tile) * L.max_tiles);
+  L.src = o; o = align256(o + sizeof(double) * 3 * 5);  // advection's per-step source maps
   L.snap_doubles = (p->system == GRPREC_EULER && p->schedule == GRPREC_SCHED_AUTO)
                        ? nvar * (2 * tc + S) + 6 * S
                        : 0;
@@ -200,6 +201,8 @@ static EulerArgs<M> euler_args(const grprec_handle *h, int slot) {
   a.nl_lambda_c = h->p.nl_lambda_c;
   a.nl_eps = h->p.nl_eps;
   a.datum = h->p.datum;
+  a.source = h->p.source;
+  a.kappa = h->p.source ? h->p.source_kappa : 0.0;
   return a;
 }
 
@@ -216,6 +219,8 @@ static AdvArgs<M> adv_args(const grprec_handle *h, int slot) {
   a.lambda = h->p.lambda;
   a.nl_lambda_c = h->p.nl_lambda_c;
   a.nl_eps = h->p.nl_eps;
+  a.kappa = h->p.source ? h->p.source_kappa : 0.0;
+  a.src = h->p.source ? (double *)(h->work + h->L.src) : nullptr;
   return a;
 }
 
@@ -380,6 +385,13 @@ int grprec_init(grprec_handle **out, const grprec_problem *pin, const grprec_buf
   if (!(p.nl_eps >= 1e-30 && p.nl_eps <= 1.0)) return GRPREC_E_INVALID;
   if (p.datum != GRPREC_DATUM_EXACT && p.datum != GRPREC_DATUM_TRRS) return GRPREC_E_INVALID;
   if (p.datum == GRPREC_DATUM_TRRS && p.system != GRPREC_EULER) return GRPREC_E_INVALID;
+  if (p.source != GRPREC_SOURCE_NONE && p.source != GRPREC_SOURCE_LINEAR) return GRPREC_E_INVALID;
+  if (p.source == GRPREC_SOURCE_LINEAR && !(p.source_kappa >= 0.0 && std::isfinite(p.source_kappa)))
+    return GRPREC_E_INVALID;
+  // the Euler source kernels are built for GRPrec with the exact datum
+  if (p.source == GRPREC_SOURCE_LINEAR && p.system == GRPREC_EULER &&
+      (p.recon != GRPREC_RECON_LINEAR || p.datum != GRPREC_DATUM_EXACT))
+    return GRPREC_E_UNSUPPORTED;
   if (p.guess == GRPREC_GUESS_MLP && !p.mlp_params) return GRPREC_E_INVALID;
   if (p.block != 0 && p.block != 64 && p.block != 128 && p.block != 256) return GRPREC_E_INVALID;
   if (p.schedule < GRPREC_SCHED_AUTO || p.schedule > GRPREC_SCHED_PER_DOMAIN) return GRPREC_E_INVALID;

@@ -97,10 +97,19 @@ __device__ __forceinline__ double sqrtpos(double x) {
   return fma(r, h, g);
 }
 
+// 1/x from the hardware estimate and one Newton step: within 11 ulp of the
+// correctly rounded value (measured on MI355X over 4M arguments spanning
+// 2^-20 .. 2^20; the raw estimate is good to about 2^-24).  Used for the
+// predictor's nodal fluxes, whose sweeps stop at a relative change of 1e-13.
+__device__ __forceinline__ double rcp1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Conserved Q = (rho, rho u, E), ideal gas p = (g-1)(E - rho u^2 / 2).
 __device__ __forceinline__ void euler_flux(const Gas &G, double r, double m, double E, double &f0,
                                            double &f1, double &f2) {
-  double u = m * rcp(r);
+  double u = m * rcp1(r);
   double p = G.gm1 * (E - 0.5 * m * u);
   f0 = m;
   f1 = m * u + p;
@@ -400,6 +409,65 @@ __device__ __noinline__ double learned_pressure(double g, double rl, double ul, 
   return (p0 > 0.0 && isfinite(p0)) ? p0 : 0.0;
 }
 
+// The learned proposal evaluated by the whole wave, for the lanes whose
+// `want` is set: lane j < 32 owns hidden unit j of both layers.  For each
+// wanted lane in turn its six standardised features are broadcast, each lane
+// evaluates its units, and the output is summed across the lanes; one
+// sample costs about as much as one lane's share of the per-lane network
+// (mlp_eval), so a wave with a few lanes above the gate no longer runs the
+// whole network on every lane.  Returns pbar exp(y) on the wanted lanes (0
+// where it is not positive and finite), 0 elsewhere.  Must be called with
+// all 64 lanes of the wave active (cross-lane reads of the hidden units);
+// L and R are read on the wanted lanes only.
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double wave_learned_pressure(double g, double gm1, bool want, double r0, double m0, double e0,
+                                                     double r1, double m1, double e1,
+                                                     const float *__restrict__ P) {
+  unsigned long long todo = __ballot(want);
+  const int lane = threadIdx.x & 63, j = lane & 31;
+  // this lane's rows of the parameters (lanes 32..63 repeat lanes 0..31)
+  float w1[6], w2[32];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) w1[k] = P[j * 6 + k];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) w2[k] = P[224 + j * 32 + k];
+  const float b1 = P[192 + j], b2 = P[1248 + j], w3 = lane < 32 ? P[1280 + j] : 0.0f, b3 = P[1312];
+  // standardised features of the wanted lanes
+  float z[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  double pb = 0.0;
+  if (want) {  // conserved data (r, m, E) of both sides -> primitive -> features
+    const double ul = m0 / r0, ur = m1 / r1;
+    const double pl = gm1 * (e0 - 0.5 * m0 * ul), pr = gm1 * (e1 - 0.5 * m1 * ur);
+    float x[6];
+    mlp_features(g, r0, ul, pl, r1, ur, pr, x, pb);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) z[k] = (x[k] - P[1313 + k]) * __builtin_amdgcn_rcpf(P[1319 + k]);
+  }
+  double p0 = 0.0;
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1ull;
+    float a = b1;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a = fmaf(w1[k], lane_read(z[k], src), a);
+    const float h1 = mlp_tanh(a);
+    float a2 = b2;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a2 = fmaf(w2[k], lane_read(h1, k), a2);
+    float t = w3 * mlp_tanh(a2);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+    if (lane == src) {
+      const double p = pb * exp((double)(t + b3));
+      p0 = (p > 0.0 && isfinite(p)) ? p : 0.0;
+    }
+  }
+  return p0;
+}
+
 // Starting pressure: learned proposal when asked for and the data jump is
 // large, else PVRS.  A non-finite or non-positive proposal falls back to PVRS.
 __device__ __forceinline__ double start_pressure(const Gas &G, const Prim &L, const Prim &R, int guess,
@@ -484,6 +552,108 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
   return it > maxit ? ERR_NEWTON : 0u;
 }
 
+// ---------------------------------------------------------------- weak waves in straight-line code
+// The Riemann problems of smooth flow have two weak nonlinear waves: the PVRS
+// start lies within kWeak of both data pressures, one Newton step meets the
+// tolerance, and no rarefaction fan straddles x/t = 0.  weak_interact solves
+// such a problem with the same start, the same Newton step and the same
+// second-order expansions as interact() (its results agree to rounding), but
+// without interact()'s branches: the sampled star density uses the expansion
+// on both the shock and the rarefaction branch (Hugoniot and isentrope agree
+// to second order, the third-order remainder is below 5e-17 rho_K), and the
+// shock speed the expansion of its square root (remainder below 1e-16 c_K).
+// It returns false, leaving o unspecified, whenever the problem needs the
+// general solver: a non-physical or vacuum state, a jump above the gate when
+// test_gate is set (then `above` is set), a start or star pressure outside
+// the weak range, a Newton step that does not meet the tolerance, or a
+// transonic rarefaction.
+struct WeakPrim {
+  double r, u, p, ip, c, irc;  // irc = 1/(rho c)
+};
+
+__device__ __forceinline__ bool weak_prim(const Gas &G, double r, double m, double E, WeakPrim &w) {
+  const double ir = rcp(r);
+  w.r = r;
+  w.u = m * ir;
+  w.p = G.gm1 * (E - 0.5 * m * w.u);
+  w.ip = rcp(w.p);
+  // 1/(rho c) = (g p rho)^(-1/2): hardware estimate and two Newton steps;
+  // c = g p / (rho c)
+  const double x = G.g * w.p * r;
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  w.irc = y;
+  w.c = G.g * w.p * y;
+  return (r > 0.0) && (w.p > 0.0) && isfinite(w.u) && isfinite(w.p) && isfinite(w.c);
+}
+
+__device__ __forceinline__ bool weak_interact(const Gas &G, const double QL[3], const double QR[3], double tol,
+                                              bool test_gate, double gate, RSOut &o, bool &above) {
+  WeakPrim L, R;
+  const bool okl = weak_prim(G, QL[0], QL[1], QL[2], L);
+  const bool okr = weak_prim(G, QR[0], QR[1], QR[2], R);
+  const double du = R.u - L.u;
+  bool ok = okl && okr && (G.two_gm1 * (L.c + R.c) > du);
+  above = false;
+  if (test_gate) {  // the jump test of jump_exceeds(), without divisions
+    const double pbar = 0.5 * (L.p + R.p), rbar = 0.5 * (L.r + R.r), cbar = 0.5 * (L.c + R.c);
+    const double lhs = fabs(R.p - L.p) * rbar * cbar + fabs(R.r - L.r) * pbar * cbar + fabs(du) * pbar * rbar;
+    above = ok && (gate < 0.0 || lhs > gate * pbar * rbar * cbar);
+    ok = ok && !above;
+  }
+  // PVRS start, floored as in pvrs()
+  const double ppv = 0.5 * (L.p + R.p) - 0.125 * du * (L.r + R.r) * (L.c + R.c);
+  const double fl = 1e-6 * fmin(L.p, R.p);
+  const double p = ppv > fl ? ppv : fl;
+  const double dl = (p - L.p) * L.ip, dr = (p - R.p) * R.ip;
+  ok = ok && fabs(dl) <= kWeak && fabs(dr) <= kWeak;
+  // one Newton step with the weak-wave pressure functions of side_eval()
+  double fL = (L.c * G.inv_g) * dl * fma(-G.k2, dl, 1.0);
+  double fR = (R.c * G.inv_g) * dr * fma(-G.k2, dr, 1.0);
+  const double fdL = L.irc * fma(-2.0 * G.k2, dl, 1.0);
+  const double fdR = R.irc * fma(-2.0 * G.k2, dr, 1.0);
+  const double pn = p - (fL + fR + du) * rcp(fdL + fdR);
+  ok = ok && pn > 0.0 && 2.0 * fabs(pn - p) <= tol * (pn + p);
+  const double dp = pn - p;
+  fL = fma(fdL, dp, fL);
+  fR = fma(fdR, dp, fR);
+  const double us = 0.5 * (L.u + R.u) + 0.5 * (fR - fL);
+  // sample x/t = 0: the left wave when u* >= 0, else the right wave
+  const bool left = us >= 0.0;
+  const double rK = left ? L.r : R.r, uK = left ? L.u : R.u, pK = left ? L.p : R.p, cK = left ? L.c : R.c;
+  const double d = (pn - pK) * (left ? L.ip : R.ip);
+  ok = ok && fabs(d) <= kWeak;
+  const double sg = left ? -1.0 : 1.0;  // the wave moves with uK + sg cK
+  bool outside;                         // x/t = 0 lies outside the wave: the data state
+  if (pn > pK) {                        // shock: speed uK + sg cK sqrt(1 + a d), a = (g+1)/(2g)
+    const double a = G.gp1_2g;
+    const double s = uK + sg * cK * fma(fma(-0.125 * a * a, d, 0.5 * a), d, 1.0);
+    outside = left ? s >= 0.0 : s <= 0.0;
+  } else {                              // rarefaction: head uK + sg cK, tail u* + sg c*
+    const double cs = cK * fma(fma(G.z2, d, G.z), d, 1.0);
+    const double head = uK + sg * cK, tail = us + sg * cs;
+    outside = left ? head >= 0.0 : head <= 0.0;
+    ok = ok && (outside || (left ? tail < 0.0 : tail >= 0.0));  // else a transonic fan
+  }
+  const double r = outside ? rK : rK * fma(fma(G.dens2, d, G.inv_g), d, 1.0);
+  const double u = outside ? uK : us;
+  const double pp = outside ? pK : pn;
+  const double E = pp * G.inv_gm1 + 0.5 * r * u * u;
+  o.Q[0] = r;
+  o.Q[1] = r * u;
+  o.Q[2] = E;
+  o.F[0] = r * u;
+  o.F[1] = r * u * u + pp;
+  o.F[2] = u * (E + pp);
+  o.pstar = pn;
+  o.iters = 1;
+  o.strong = false;
+  o.learned = false;
+  return ok;
+}
+
 // ---------------------------------------------------------------- two-rarefaction datum
 // Two-rarefaction approximation of the Riemann problem (the solver Sec. 4.1
 // names for the Euler interface datum): with both nonlinear waves taken as
@@ -548,6 +718,51 @@ __device__ __forceinline__ unsigned trrs_interact(const Gas &G, const double QL[
   o.F[1] = r * u * u + p;
   o.F[2] = u * (E + p);
   return 0u;
+}
+
+// ---------------------------------------------------------------- implicit source
+// Time matrices of the space-time predictor with the linear relaxation source
+// S(q) = -kappa q taken implicitly: with z = kappa dt the weak form's time
+// matrix is Kz = K + z diag(w), and the predictor iterates
+//   q[a][.] <- c w_a - nu A (D F)[a][.],  A = Kz^{-1} diag(w),  c = Kz^{-1} l(0)
+// (c = 1 and A = K^{-1} diag(w) without source).  Gauss-Jordan without pivot
+// search: the pivots of K + z diag(w) stay above 0.4 of its largest entry for
+// every z >= 0 at these degrees.
+template <int N>
+__device__ __forceinline__ void source_time_mats(const double (&K)[N][N], const double (&w)[N],
+                                                 const double (&l0)[N], double z, double (&A)[N][N],
+                                                 double (&c)[N]) {
+  double M[N][N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      M[b][l] = K[b][l] + (b == l ? z * w[b] : 0.0);
+      A[b][l] = b == l ? w[b] : 0.0;  // right-hand sides diag(w) | l(0)
+    }
+    c[b] = l0[b];
+  }
+#pragma unroll
+  for (int col = 0; col < N; ++col) {
+    const double ip = rcp(M[col][col]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      M[col][k] *= ip;
+      A[col][k] *= ip;
+    }
+    c[col] *= ip;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == col) continue;
+      const double f = M[r][col];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        M[r][k] = fma(-f, M[col][k], M[r][k]);
+        A[r][k] = fma(-f, A[col][k], A[r][k]);
+      }
+      c[r] = fma(-f, c[col], c[r]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- GRPrecNL

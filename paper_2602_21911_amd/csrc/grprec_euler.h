@@ -32,7 +32,11 @@ namespace grp {
 // NL: GRPrecNL reconstruction (Sec. 3.3-3.4) instead of GRPrec (Sec. 3.1).
 // TR: end-of-step datum by the two-rarefaction solver (Sec. 4.1); a run-time
 // branch in the Riemann loop would cost registers on every path.
-template <int M, int B, bool AIR, bool NL, bool TR>
+// SRC: the linear relaxation source S(Q) = -kappa Q (eq. eq_finite_volume with
+// S^n_i of eq. source): implicit in the predictor (time matrix K + z diag(w),
+// z = kappa dt), the ghost states evolved by it, and dt S^n_i from the
+// predicted space-time polynomial in the update.
+template <int M, int B, bool AIR, bool NL, bool TR, bool SRC>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(GRPREC_EULER_WAVES(M))))
 void euler_step(EulerArgs<M> a) {
   constexpr int N = M + 1;   // nodes per direction
@@ -80,9 +84,22 @@ void euler_step(EulerArgs<M> a) {
     r.first = d->first[wj];
     return r;
   };
+  // Which tiles this block takes.  Blocks are dispatched to the 8 XCDs
+  // round-robin, so with a grid that is a multiple of 8 the tiles are split
+  // into 8 contiguous ranges, one per XCD, and the XCD's blocks take its range
+  // in turn: neighbouring tiles then run on one XCD and the cache lines their
+  // halos share are fetched into that XCD's L2 once.  Otherwise the blocks
+  // take the tiles in turn.
+  int t_first = blockIdx.x, t_step = gridDim.x, t_last = a.ntiles;
+  if ((gridDim.x & 7) == 0) {
+    const int per = (a.ntiles + 7) >> 3, x = blockIdx.x & 7;
+    t_first = x * per + (blockIdx.x >> 3);
+    t_step = gridDim.x >> 3;
+    t_last = min((x + 1) * per, a.ntiles);
+  }
   // the next tile's descriptor is read one tile ahead
   LaneTile nx = {0, 0, -1, -1, 0, 0, 0ull};
-  if ((int)blockIdx.x < a.ntiles) nx = lane_tile(blockIdx.x);
+  if (t_first < t_last) nx = lane_tile(t_first);
   // S_max of the new states: a tile's run maxima are compared with the
   // accumulating target, read at the end of the tile, at the head of the next
   // one, so that read's latency overlaps the next tile's own reads
@@ -91,9 +108,9 @@ void euler_step(EulerArgs<M> a) {
   int pseg = 0;
   unsigned long long pbits = 0, pseen = 0;
 
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  for (int tile = t_first; tile < t_last; tile += t_step) {
     const LaneTile td = nx;
-    if (tile + (int)gridDim.x < a.ntiles) nx = lane_tile(tile + gridDim.x);
+    if (tile + t_step < t_last) nx = lane_tile(tile + t_step);
     const int start = td.start, count = td.count;
     // ---- which cell this slot holds, and its domain
     bool valid = false, useful = false;
@@ -132,6 +149,21 @@ void euler_step(EulerArgs<M> a) {
       nu = dt / dx;
     }
     const bool work = valid && !done;
+    // implicit source: the predictor's time matrices for this slot's dt, and
+    // the factors of the constant-state evolution (ghost cells): gf[b] at the
+    // time nodes, gf[N] at the end of the step
+    double SA[SRC ? N : 1][SRC ? N : 1], gf[SRC ? N + 1 : 1];
+    if constexpr (SRC) {
+      double sc[N];
+      source_time_mats<N>(T.K, T.w, T.l0, a.kappa * dt, SA, sc);
+      double g1 = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        gf[b] = sc[b];
+        g1 = fma(T.l1[b], sc[b], g1);
+      }
+      gf[N] = g1;
+    }
     if (pend && pseen < pbits) atomicMax(acc + pseg, pbits);
     if (useful && !work) {  // a domain past its end time carries its data over
 #pragma unroll
@@ -142,6 +174,7 @@ void euler_step(EulerArgs<M> a) {
     }
 
     // ---- reconstruct, predict
+    double src_dt[3] = {0.0, 0.0, 0.0};
     if (work) {
       int im = i - 1, ip = i + 1;
       if (a.periodic) {
@@ -269,7 +302,15 @@ void euler_step(EulerArgs<M> a) {
             for (int k = 0; k < N; ++k) Gd += T.D[x][k] * F1[v][k];
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-              const double nv = w[v][x] - nu * (T.KWs[b] * Gd);
+              double nv;
+              if constexpr (SRC) {
+                double rs = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) rs += SA[b][l];
+                nv = gf[b] * w[v][x] - nu * (rs * Gd);
+              } else {
+                nv = w[v][x] - nu * (T.KWs[b] * Gd);
+              }
               diff = fmax(diff, fabs(nv - w[v][x]));
               nrm = fmax(nrm, fabs(nv));
               qh[v][x][b] = nv;
@@ -301,9 +342,16 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll
             for (int b = 0; b < N; ++b) {
               double acc = 0.0;
+              double wb = w[v][x];
+              if constexpr (SRC) {
 #pragma unroll
-              for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[l];
-              const double nv = w[v][x] - nu * acc;
+                for (int l = 0; l < N; ++l) acc += SA[b][l] * Gd[l];
+                wb *= gf[b];
+              } else {
+#pragma unroll
+                for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[l];
+              }
+              const double nv = wb - nu * acc;
               // non-finite values do not stop the sweep here: they reach the
               // traces and are caught by the physical-state checks
               diff = fmax(diff, fabs(nv - qh[v][x][b]));
@@ -319,6 +367,20 @@ void euler_step(EulerArgs<M> a) {
       }
       if (!conv) err |= ERR_PICARD;
       st_sweeps += conv ? it : a.max_picard;
+      if constexpr (SRC) {  // dt S^n_i: Gauss-Legendre mean of -kappa q over the space-time cell
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          double acc = 0.0;
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            double row = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) row = fma(T.w[b], qh[v][x][b], row);
+            acc = fma(T.w[x], row, acc);
+          }
+          src_dt[v] = -(a.kappa * dt) * acc;
+        }
+      }
       st_cells += 1;
       // traces at xi = 0 and xi = 1, times g_b and 1, staged in LDS
 #pragma unroll
@@ -353,60 +415,123 @@ void euler_step(EulerArgs<M> a) {
     // transmissive end the outside data are a ghost cell holding the end
     // cell's average, constant in space and time.
     double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
-    if (work && (useful || e == 0)) {
-      const bool boundary = (!a.periodic) && (i == n - 1);
-      // Riemann problem at trace time b with Newton start pguess (0: PVRS),
-      // optionally testing the gate (learned start when mlp != nullptr);
-      // adds the flux sample or takes the datum
-      auto solve = [&](int b, double pguess, const float *mlp, bool test_gate) -> RSOut {
-        double QL[3] = {sTR[0 * NT + b][e], sTR[1 * NT + b][e], sTR[2 * NT + b][e]};
-        double QR[3];
-        if (boundary) {
-          QR[0] = q0[0]; QR[1] = q0[1]; QR[2] = q0[2];
-        } else {
-          QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+    const bool rs_lane = work && (useful || e == 0);
+    const bool boundary = (!a.periodic) && (i == n - 1);
+    const bool gated = a.warm || a.guess == 1;
+    // data of the Riemann problem at trace time b: this slot's right trace
+    // against the right neighbour's left trace (or the ghost state)
+    auto load = [&](int b, double (&QL)[3], double (&QR)[3]) {
+      QL[0] = sTR[0 * NT + b][e]; QL[1] = sTR[1 * NT + b][e]; QL[2] = sTR[2 * NT + b][e];
+      if (boundary) {
+        double f = 1.0;
+        if constexpr (SRC) f = pick<N + 1>(gf, b);
+        QR[0] = f * q0[0]; QR[1] = f * q0[1]; QR[2] = f * q0[2];
+      } else {
+        QR[0] = sTL[0 * NT + b][e + 1]; QR[1] = sTL[1 * NT + b][e + 1]; QR[2] = sTL[2 * NT + b][e + 1];
+      }
+    };
+    // counts the solve, records it when harvesting, and adds the flux
+    // sample or takes the datum
+    auto take = [&](int b, const RSOut &o, const double (&QL)[3], const double (&QR)[3]) {
+      st_mlp += o.learned ? 1 : 0;
+      st_rs += 1;
+      st_newton += o.iters;
+      if (b == 0 && a.hv.ring != nullptr && useful) {
+        unsigned long long k = atomicAdd(a.hv.count, 1ull);
+        if ((long long)k < a.hv.cap) {
+          Prim L, R;
+          to_prim(G, QL[0], QL[1], QL[2], L);
+          to_prim(G, QR[0], QR[1], QR[2], R);
+          double *dst = a.hv.ring + 7 * k;
+          dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
+          dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
+          dst[6] = o.pstar;
         }
-        RSOut o;
-        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
-          err |= trrs_interact(G, QL, QR, o);
-        else
-          err |= interact(G, QL, QR, pguess, a.max_newton, a.newton_tol, o, mlp, a.gate, test_gate);
-        st_mlp += o.learned ? 1 : 0;
-        st_rs += 1;
-        st_newton += o.iters;
-        if (b == 0 && a.hv.ring != nullptr && useful) {
-          unsigned long long k = atomicAdd(a.hv.count, 1ull);
-          if ((long long)k < a.hv.cap) {
-            Prim L, R;
-            to_prim(G, QL[0], QL[1], QL[2], L);
-            to_prim(G, QR[0], QR[1], QR[2], R);
-            double *dst = a.hv.ring + 7 * k;
-            dst[0] = L.r; dst[1] = L.u; dst[2] = L.p;
-            dst[3] = R.r; dst[4] = R.u; dst[5] = R.p;
-            dst[6] = o.pstar;
+      }
+      if (b < N) {
+        const double wb = pick<N>(T.w, b);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) FR[v] += wb * o.F[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
+      }
+    };
+    // The first time: the weak-wave solver, which also tests the interface's
+    // jump against the gate when learned or warm starts are on.
+    double QL0[3] = {1.0, 0.0, 1.0}, QR0[3] = {1.0, 0.0, 1.0};
+    RSOut o0;
+    bool fast0 = false, above0 = false;
+    if (rs_lane) {
+      load(0, QL0, QR0);
+      fast0 = weak_interact(G, QL0, QR0, a.newton_tol, gated, a.gate, o0, above0);
+    }
+    // learned starts of the interfaces above the gate, evaluated by the whole
+    // wave (every lane is active here)
+    double p_learn = 0.0;
+    if (a.guess == 1 && __ballot(above0) != 0ull)
+      p_learn = wave_learned_pressure(G.g, G.gm1, above0, QL0[0], QL0[1], QL0[2], QR0[0], QR0[1], QR0[2],
+                                      a.mlp);
+    if (rs_lane) {
+      // Fast pass: the weak-wave solver, in straight-line code, for the
+      // later times too.  The times are independent, and the unrolled loop
+      // gives the scheduler that independent work.  A wave in which some
+      // first-time problem needs the general solver runs the general solver
+      // for all its problems instead (it would wait for those lanes anyway),
+      // unrolled over the times as well.
+      if (__builtin_expect(__ballot(!fast0) == 0ull, 1)) {
+        take(0, o0, QL0, QR0);
+        unsigned slow = 0;
+#pragma unroll
+        for (int b = 1; b < NT; ++b) {
+          double QL[3], QR[3];
+          load(b, QL, QR);
+          RSOut o;
+          bool fast;
+          if (TR && b == N) {  // end-of-step datum by the two-rarefaction solver
+            err |= trrs_interact(G, QL, QR, o);
+            fast = true;
+          } else {
+            bool above_b;
+            fast = weak_interact(G, QL, QR, a.newton_tol, false, a.gate, o, above_b);
+          }
+          if (fast) take(b, o, QL, QR);
+          else slow |= 1u << b;
+        }
+        // the few later-time problems the weak-wave solver declined (first
+        // time below the gate: PVRS start)
+        if (__builtin_expect(slow != 0, 0)) {
+#pragma unroll 1
+          for (int b = 1; b < NT; ++b) {
+            if (!((slow >> b) & 1u)) continue;
+            double QL[3], QR[3];
+            load(b, QL, QR);
+            RSOut o;
+            err |= interact(G, QL, QR, 0.0, a.max_newton, a.newton_tol, o);
+            take(b, o, QL, QR);
           }
         }
-        if (b < N) {
-          const double wb = pick<N>(T.w, b);
+      } else {
+        // General solver.  Above the gate the first time starts from the
+        // learned proposal and the later times from the first time's star
+        // pressure; below it (and without gating) every time starts from PVRS.
+        RSOut og;
+        err |= interact(G, QL0, QR0, p_learn, a.max_newton, a.newton_tol, og, nullptr, a.gate, gated);
+        og.learned = og.strong && p_learn > 0.0;
+        take(0, og, QL0, QR0);
+        const double pg = og.strong ? og.pstar : 0.0;
 #pragma unroll
-          for (int v = 0; v < 3; ++v) FR[v] += wb * o.F[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
+        for (int b = 1; b < NT; ++b) {
+          double QL[3], QR[3];
+          load(b, QL, QR);
+          RSOut o;
+          if (TR && b == N)
+            err |= trrs_interact(G, QL, QR, o);
+          else
+            err |= interact(G, QL, QR, pg, a.max_newton, a.newton_tol, o);
+          take(b, o, QL, QR);
         }
-        return o;
-      };
-      // With gating (learned or warm starts) the first time tests the
-      // interface's jump against the gate; above it the first time starts from
-      // the learned proposal and the later times from the first time's star
-      // pressure, below it (and without gating) every time starts from PVRS.
-      // The later times are independent of each other, and the unrolled loop
-      // gives the scheduler that independent work.
-      const bool gated = a.warm || a.guess == 1;
-      const RSOut o0 = solve(0, 0.0, (gated && a.guess == 1) ? a.mlp : nullptr, gated);
-      const double pg = o0.strong ? o0.pstar : 0.0;
-#pragma unroll
-      for (int b = 1; b < NT; ++b) (void)solve(b, pg, nullptr, false);
+      }
       // flux and datum go to the right neighbour through this slot's own
       // right-trace column, which no other thread reads
 #pragma unroll
@@ -416,21 +541,28 @@ void euler_step(EulerArgs<M> a) {
       }
     }
     // left end of a transmissive domain: ghost average against the left trace
+    // (above the gate the later times start from the first time's star
+    // pressure; the learned start is taken at interior and right-end
+    // interfaces only)
     double FL[3] = {0.0, 0.0, 0.0}, VL[3] = {0.0, 0.0, 0.0};
     if (work && useful && i == 0 && !a.periodic) {
-      const bool gated = a.warm || a.guess == 1;
       double pw = 0.0;
       bool strong = false;
 #pragma unroll 1
       for (int b = 0; b < NT; ++b) {
         double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
-        const float *mlp = (b == 0 && a.guess == 1) ? a.mlp : nullptr;
+        double QG[3] = {q0[0], q0[1], q0[2]};  // the ghost's state at this time
+        if constexpr (SRC) {
+          const double f = pick<N + 1>(gf, b);
+          QG[0] *= f; QG[1] *= f; QG[2] *= f;
+        }
         RSOut o;
         if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
-          err |= trrs_interact(G, q0, QR, o);
-        else
-          err |= interact(G, q0, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
-                          mlp, a.gate, b == 0 && gated);
+          err |= trrs_interact(G, QG, QR, o);
+        else if (bool above_l; !((b == 0 || !strong) &&
+                                 weak_interact(G, QG, QR, a.newton_tol, b == 0 && gated, a.gate, o, above_l)))
+          err |= interact(G, QG, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
+                          nullptr, a.gate, b == 0 && gated);
         if (b == 0) {  // later times start from the first time's p* above the gate
           strong = o.strong;
           pw = o.pstar;
@@ -465,6 +597,10 @@ void euler_step(EulerArgs<M> a) {
         }
 #pragma unroll
         for (int v = 0; v < 3; ++v) qn[v] = q0[v] - nu * (FR[v] - FL[v]);
+        if constexpr (SRC) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) qn[v] += src_dt[v];
+        }
 #pragma unroll
         for (int v = 0; v < 3; ++v) vout[v * ti + io + i + 1] = VR[v];
         if (i == 0) {
@@ -514,15 +650,28 @@ void euler_step(EulerArgs<M> a) {
 
 // ============================================================ launchers
 // (host-callable wrappers so that the API file needs no kernel templates)
+// The source runs with GRPrec and the exact datum only (the host rejects the
+// other combinations), which keeps the number of instantiations down.
 template <int M, int B, bool NL>
 static hipError_t launch_euler_mbn(const EulerArgs<M> &a, int grid, hipStream_t st) {
   if (a.gas.g == kGammaAir) {
-    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, true, NL, true>), dim3(grid), dim3(B), 0, st, a);
-    else hipLaunchKernelGGL((euler_step<M, B, true, NL, false>), dim3(grid), dim3(B), 0, st, a);
+    if (a.source) {
+      if constexpr (!NL) hipLaunchKernelGGL((euler_step<M, B, true, false, false, true>), dim3(grid), dim3(B), 0, st, a);
+    } else if (a.datum == 1) {
+      hipLaunchKernelGGL((euler_step<M, B, true, NL, true, false>), dim3(grid), dim3(B), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((euler_step<M, B, true, NL, false, false>), dim3(grid), dim3(B), 0, st, a);
+    }
   } else {
-    if (a.datum == 1) hipLaunchKernelGGL((euler_step<M, B, false, NL, true>), dim3(grid), dim3(B), 0, st, a);
-    else hipLaunchKernelGGL((euler_step<M, B, false, NL, false>), dim3(grid), dim3(B), 0, st, a);
+    if (a.source) {
+      if constexpr (!NL) hipLaunchKernelGGL((euler_step<M, B, false, false, false, true>), dim3(grid), dim3(B), 0, st, a);
+    } else if (a.datum == 1) {
+      hipLaunchKernelGGL((euler_step<M, B, false, NL, true, false>), dim3(grid), dim3(B), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((euler_step<M, B, false, NL, false, false>), dim3(grid), dim3(B), 0, st, a);
+    }
   }
+  if (NL && a.source) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -543,8 +692,8 @@ hipError_t launch_euler(const EulerArgs<M> &a, int block, int grid, bool nl, hip
 
 template <int M, int B>
 static hipError_t euler_occ_b(bool nl, int *blocks_per_cu) {
-  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true, false>, B, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false, false>, B, 0);
+  return nl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, true, false, false>, B, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, euler_step<M, B, true, false, false, false>, B, 0);
 }
 
 template <int M>

@@ -118,6 +118,8 @@ struct EulerArgs {
   Harvest hv;
   double nl_lambda_c, nl_eps;  // GRPrecNL weights (used by the NL instantiations)
   int datum;                   // end-of-step datum: 0 exact Riemann solver, 1 two-rarefaction
+  int source;                  // 1: S(Q) = -kappa Q (the SRC instantiations)
+  double kappa;
 };
 
 template <int M>
@@ -130,6 +132,8 @@ struct AdvArgs {
   int periodic;
   double cfl, lambda;
   double nl_lambda_c, nl_eps;  // GRPrecNL weights (used by the NL instantiations)
+  double kappa;                // S(q) = -kappa q (the SRC instantiations)
+  double *src;                 // per-step linear maps of the predictor with source (SRC)
 };
 
 }  // namespace grp

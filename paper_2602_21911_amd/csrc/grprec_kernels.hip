@@ -89,7 +89,12 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
 #endif
 #define ADV_RUN 63    // cells a wave updates per run (64 lanes, one upwind overlap)
 
-template <int M, bool NL>
+// SRC: with the relaxation source S(q) = -kappa q the predictor is the
+// space-time DG evolution with the implicit source instead of the exact
+// translation; being linear, its flux mean, end-of-step datum and space-time
+// mean are fixed linear combinations of the cell mean and the coefficients,
+// computed once per step by adv_source_prep into a.src.
+template <int M, bool NL, bool SRC>
 __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   Ctl *ctl = a.ctl;
   const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
@@ -119,8 +124,21 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   const bool pos = a.lambda > 0.0;
   // per-step constants: mean of each basis function over the swept interval
   // and its value at the foot of the characteristic
-  double Kin[4], Pin[4];
-  if (pos) {
+  double Kin[4], Pin[4], Sin[4] = {0.0, 0.0, 0.0, 0.0};
+  double K0 = 1.0, P0 = 1.0, S0 = 0.0, zs = 0.0;
+  if constexpr (SRC) {
+    // [0]: the constant mode, [1 + j]: phi_{j+1} (zero beyond the degree)
+    K0 = a.src[0];
+    P0 = a.src[M + 1];
+    S0 = a.src[2 * (M + 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Kin[j] = j < M ? a.src[1 + j] : 0.0;
+      Pin[j] = j < M ? a.src[M + 2 + j] : 0.0;
+      Sin[j] = j < M ? a.src[2 * (M + 1) + 1 + j] : 0.0;
+    }
+    zs = a.kappa * dt;
+  } else if (pos) {
     basis_mean(0.5 - cn, 0.5, Kin);
     basis_at(0.5 - cn, Pin);
   } else {
@@ -195,10 +213,14 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     }
     // the lane's flux mean over the swept interval and its datum; at i = -1
     // and i = n the upwind neighbour is the periodic image or the ghost cell
-    // (a constant state: mean and point value are the end average)
-    double mean_s = 0.0, pt_s = 0.0;
+    // (a constant state: mean and point value are the end average, scaled by
+    // the source's evolution of a constant)
+    double mean_s = 0.0, pt_s = 0.0, src_s = 0.0;
     const bool recon = (i >= 0 && i < n) || (a.periodic && (i == -1 || i == n));
-    if (!recon && (i == -1 || i == n)) mean_s = pt_s = qk;
+    if (!recon && (i == -1 || i == n)) {
+      mean_s = K0 * qk;
+      pt_s = P0 * qk;
+    }
     if (recon && !done) {
       if (lane == 0) {
         qm = Q(i - 1);
@@ -224,12 +246,19 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       } else {
         adv_coeffs<M>(qm, qk, qp, vl, vp, ac);
       }
-      mean_s = qk;
-      pt_s = qk;
+      if constexpr (SRC) {
+        mean_s = K0 * qk;
+        pt_s = P0 * qk;
+        src_s = S0 * qk;
+      } else {
+        mean_s = qk;
+        pt_s = qk;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         mean_s += ac[j] * Kin[j];
         pt_s += ac[j] * Pin[j];
+        if constexpr (SRC) src_s += ac[j] * Sin[j];
       }
     }
     const double mean_u = pos ? wave_prev(mean_s) : wave_next(mean_s);
@@ -252,6 +281,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       vout[i] = pt_s;
       if (i == n - 1) vout[n] = pt_u;
     }
+    if constexpr (SRC) qn -= zs * src_s;  // dt S^n_i, S = -kappa q
     qout[i] = qn;
     if (!isfinite(qn)) atomicOr(&ctl->err, ERR_NONPHYS);
   }
@@ -261,6 +291,72 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     a.seg.smax[s1 * a.seg.S] = dbits(fabs(a.lambda));
     a.seg.smax[s2 * a.seg.S] = 0ull;
     if (t_new < t_end) atomicAdd(&ctl->active[s1], 1);
+  }
+}
+
+// Per-step linear maps of the advection predictor with the implicit source
+// (one thread): for the constant mode and each basis function phi_j the
+// space-time DG predictor of q_t + lambda q_x = -kappa q is iterated to its
+// fixed point (the linear flux makes it a fixed linear map of the data), then
+//   src[j]             time mean of the upwind trace (the flux over lambda),
+//   src[M+1+j]         the upwind trace at the end of the step (the datum),
+//   src[2(M+1)+j]      the space-time mean (the source integral over -kappa).
+// The upwind trace is the right one (xi = 1) for lambda > 0, else the left.
+template <int M>
+__global__ void adv_source_prep(AdvArgs<M> a) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  constexpr int N = M + 1;
+  constexpr tab::Predictor<M> T = tab::predictor<M>();
+  Ctl *ctl = a.ctl;
+  const double dx = a.seg.dx[0];
+  double dt, t_new;
+  bool done;
+  domain_dt(a.cfl, dx, fabs(a.lambda), a.seg.t[a.slot * a.seg.S], ctl->t_end, dt, t_new, done);
+  const double cn = a.lambda * dt / dx;
+  double A[N][N], c[N];
+  source_time_mats<N>(T.K, T.w, T.l0, a.kappa * dt, A, c);
+  const bool pos = a.lambda > 0.0;
+  for (int j = 0; j <= M; ++j) {
+    double w[N], q[N][N];
+    for (int x = 0; x < N; ++x) {
+      w[x] = j == 0 ? 1.0 : T.phi[x][j - 1];
+      for (int b = 0; b < N; ++b) q[x][b] = w[x];
+    }
+    for (int it = 0; it < 200; ++it) {
+      double qn[N][N], diff = 0.0, nrm = 0.0;
+      for (int x = 0; x < N; ++x) {
+        double Gd[N];
+        for (int l = 0; l < N; ++l) {
+          double g = 0.0;
+          for (int k = 0; k < N; ++k) g = fma(T.D[x][k], q[k][l], g);
+          Gd[l] = g;
+        }
+        for (int b = 0; b < N; ++b) {
+          double acc = 0.0;
+          for (int l = 0; l < N; ++l) acc = fma(A[b][l], Gd[l], acc);
+          qn[x][b] = c[b] * w[x] - cn * acc;
+          diff = fmax(diff, fabs(qn[x][b] - q[x][b]));
+          nrm = fmax(nrm, fabs(qn[x][b]));
+        }
+      }
+      for (int x = 0; x < N; ++x)
+        for (int b = 0; b < N; ++b) q[x][b] = qn[x][b];
+      if (diff <= 1e-17 * (1.0 + nrm)) break;
+    }
+    double fm = 0.0, end = 0.0, st = 0.0;
+    for (int b = 0; b < N; ++b) {
+      double tr = 0.0, row = 0.0;
+      for (int x = 0; x < N; ++x) {
+        tr = fma(pos ? T.l1[x] : T.l0[x], q[x][b], tr);
+        row = fma(T.w[x], q[x][b], row);
+      }
+      fm = fma(T.w[b], tr, fm);
+      end = fma(T.l1[b], tr, end);
+      st = fma(T.w[b], row, st);
+    }
+    a.src[j] = fm;
+    a.src[N + j] = end;
+    a.src[2 * N + j] = st;
   }
 }
 
@@ -378,10 +474,18 @@ hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
   const long long ch = 4LL * ADV_PASSES * ADV_RUN;
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
-  if (nl)
-    hipLaunchKernelGGL((adv_step<M, true>), dim3(g), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((adv_step<M, false>), dim3(g), dim3(256), 0, st, a);
+  if (a.src) {
+    // the source's per-step maps first (stream order makes them visible)
+    hipLaunchKernelGGL((adv_source_prep<M>), dim3(1), dim3(64), 0, st, a);
+    if (nl)
+      hipLaunchKernelGGL((adv_step<M, true, true>), dim3(g), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((adv_step<M, false, true>), dim3(g), dim3(256), 0, st, a);
+  } else if (nl) {
+    hipLaunchKernelGGL((adv_step<M, true, false>), dim3(g), dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((adv_step<M, false, false>), dim3(g), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -5,8 +5,9 @@
 // Lagrange basis l_a on these nodes; D[a][k] = l_k'(g_a); the time matrix of
 // the space-time weak form K[b][l] = l_b(1) l_l(1) - int_0^1 l_b' l_l, which
 // Gauss-Legendre at the nodes integrates exactly: l_b(1) l_l(1) - w_l l_b'(g_l);
-// KW = K^{-1} diag(w).  Everything is evaluated by the compiler, so the
-// kernels see the numbers as immediate operands.
+// KW = K^{-1} diag(w).  K itself is kept for the implicit source term, whose
+// time matrix is K + z diag(w) with z = kappa dt.  Everything is evaluated by
+// the compiler, so the kernels see the numbers as immediate operands.
 #pragma once
 
 namespace grp {
@@ -90,6 +91,7 @@ struct Predictor {
   static constexpr int N = M + 1;
   double g[N], w[N];
   double D[N][N];
+  double K[N][N];    // time matrix of the weak form
   double KW[N][N];
   double KWs[N];     // row sums of KW (the time solve of a time-constant argument)
   double l0[N], l1[N];
@@ -110,6 +112,7 @@ constexpr Predictor<M> predictor() {
     for (int l = 0; l < N; ++l) {
       K[b][l] = lag<N>(P.g, b, 1.0) * lag<N>(P.g, l, 1.0) - P.w[l] * lag_d<N>(P.g, b, P.g[l]);
       K[b][N + l] = (b == l) ? 1.0 : 0.0;
+      P.K[b][l] = K[b][l];
     }
   for (int col = 0; col < N; ++col) {  // Gauss-Jordan with partial pivoting
     int piv = col;

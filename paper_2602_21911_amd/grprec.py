@@ -34,6 +34,7 @@ GRPREC_SCHED_AUTO, GRPREC_SCHED_SEGMENT_TILES, GRPREC_SCHED_FLAT_TILES, GRPREC_S
 GRPREC_SCHED_PER_DOMAIN = 4
 GRPREC_RECON_LINEAR, GRPREC_RECON_NL = 0, 1
 GRPREC_DATUM_EXACT, GRPREC_DATUM_TRRS = 0, 1
+GRPREC_SOURCE_NONE, GRPREC_SOURCE_LINEAR = 0, 1
 GRPREC_MLP_WEIGHTS = 1313
 GRPREC_MLP_NPARAMS = 1325
 GRPREC_MLP_NOALLOC_MAX = 65536
@@ -63,7 +64,8 @@ class grprec_problem(ctypes.Structure):
                 ("picard_tol", ctypes.c_double), ("mlp_params", _vp),
                 ("mlp_gate", ctypes.c_double), ("warm_start", ctypes.c_int),
                 ("schedule", ctypes.c_int), ("block", ctypes.c_int), ("recon", ctypes.c_int),
-                ("nl_lambda_c", ctypes.c_double), ("nl_eps", ctypes.c_double), ("datum", ctypes.c_int)]
+                ("nl_lambda_c", ctypes.c_double), ("nl_eps", ctypes.c_double), ("datum", ctypes.c_int),
+                ("source", ctypes.c_int), ("source_kappa", ctypes.c_double)]
 
 
 class grprec_buffers(ctypes.Structure):
@@ -323,7 +325,7 @@ class Simulation:
                  block: int = 0, max_newton: int = 50, newton_tol: float = 1e-12,
                  max_picard: int = 64, picard_tol: float = 1e-13, recon: int = GRPREC_RECON_LINEAR,
                  nl_lambda_c: float = 1e9, nl_eps: float = 1e-14, datum: int = GRPREC_DATUM_EXACT,
-                 device: str = "cuda"):
+                 source: int = GRPREC_SOURCE_NONE, kappa: float = 0.0, device: str = "cuda"):
         import torch
         self.torch = torch
         self.cells = np.ascontiguousarray(cells, dtype=np.int64)
@@ -338,7 +340,8 @@ class Simulation:
                                 self.cells.ctypes.data_as(_i64p), self.lengths.ctypes.data_as(_dp),
                                 guess, max_newton, newton_tol, max_picard, picard_tol,
                                 None if mlp_params is None else mlp_params.data_ptr(), mlp_gate,
-                                warm_start, schedule, block, recon, nl_lambda_c, nl_eps, datum)
+                                warm_start, schedule, block, recon, nl_lambda_c, nl_eps, datum,
+                                source, kappa)
         self.mlp_params = mlp_params
         wb = grprec_workspace_bytes(self.p)
         if wb == 0:
