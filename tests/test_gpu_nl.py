@@ -160,24 +160,31 @@ def test_euler_nl_network_parity(G, schedule, block):
         sim.close()
 
 
-def test_sod_grprecnl_reports_failure(G):
-    """Both sides fail on Sod under these readings of GRPrecNL: orders 3-4
-    at the first step, order 2 a few steps later."""
-    dx, q, vl, vr = I.euler_shock_tube(100)
-    for order in (2, 3, 4):
-        print(f"Sod NL order {order}", flush=True)
-        c = _ocfg(oracle.EULER, order, oracle.TRANSMISSIVE, 10.0)
-        v = oracle.init_interfaces(c, vl, vr)
-        with pytest.raises(oracle.OracleError):
-            oracle.run(c, dx, q, v, 0.0, 0.2, max_steps=10)
-        sim = _sim(G, G.GRPREC_EULER, order, [100], [1.0], q, vl, vr, G.GRPREC_BC_TRANSMISSIVE, 10.0,
-                   schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=64)
-        try:
-            with pytest.raises(G.GrprecError) as ei:
-                sim.run(0.2, 10)
-            assert ei.value.code in (G.GRPREC_E_PREDICTOR, G.GRPREC_E_NONPHYSICAL, G.GRPREC_E_NEWTON)
-        finally:
-            sim.close()
+@pytest.mark.parametrize("name", ["sod", "123"])
+def test_paper_riemann_problems_reported_like_the_oracle(G, name):
+    """The paper's Sod (x_c = 0.3, C_CFL 0.9) and 123 (C_CFL 0.9 at orders
+    2-3, 0.7 at 4-5) set-ups with GRPrecNL: under these readings both sides
+    stop within three steps (see the oracle pins for the mechanism); the GPU
+    reports the same failure instead of running on."""
+    left, right, xc, t_end = {"sod": ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.3, 0.2),
+                              "123": ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.5, 0.15)}[name]
+    dx, q, vl, vr = I.euler_shock_tube(100, left=left, right=right, xc=xc)
+    for order in (2, 3, 4, 5):
+        cfl = 0.7 if (name == "123" and order >= 4) else 0.9
+        for lam_c in (oracle.LAMBDA_C_PRINTED, oracle.LAMBDA_C_TABLE):
+            print(f"{name} NL order {order} lambda_C {lam_c}", flush=True)
+            c = _ocfg(oracle.EULER, order, oracle.TRANSMISSIVE, lam_c, cfl=cfl)
+            v = oracle.init_interfaces(c, vl, vr)
+            with pytest.raises(oracle.OracleError):
+                oracle.run(c, dx, q, v, 0.0, t_end, max_steps=3)
+            sim = _sim(G, G.GRPREC_EULER, order, [100], [1.0], q, vl, vr, G.GRPREC_BC_TRANSMISSIVE, lam_c,
+                       cfl=cfl, schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=64)
+            try:
+                with pytest.raises(G.GrprecError) as ei:
+                    sim.run(t_end, 3)
+                assert ei.value.code in (G.GRPREC_E_PREDICTOR, G.GRPREC_E_NONPHYSICAL, G.GRPREC_E_NEWTON)
+            finally:
+                sim.close()
 
 
 def test_nl_parameter_validation(G):

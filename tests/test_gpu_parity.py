@@ -262,3 +262,52 @@ def test_network_parity_order5(G, schedule, block):
         c0, c1 = net.cell_off[s], net.cell_off[s + 1]
         assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= ONE_STEP * 10, s
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= ONE_STEP * 10, s
+
+
+# ------------------------------------------------------------- configured end times
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_euler_density_wave_to_configured_end_time(G, order):
+    """The Euler density wave (rho = 1 + 0.2 sin 2 pi x, u = 1, p = 1,
+    periodic) run to its configured end time t = 2 (about a thousand steps at
+    200 cells): the t_end bar holds after the whole run, and the GPU took the
+    oracle's number of steps and landed on t = 2."""
+    n = 200
+    dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=1.0)
+    c = oracle_cfg(oracle.EULER, order, oracle.PERIODIC)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _gpu_sim(G, G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, G.GRPREC_BC_PERIODIC,
+                   schedule=G.GRPREC_SCHED_SEGMENT_TILES, block=64)
+    try:
+        print(f"density wave to t = 2, order {order}", flush=True)
+        sim.run(2.0)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 2.0)
+        qg, vg, t, steps = sim.numpy_state()
+        assert t == tr == 2.0 and steps == kr and kr > 900
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
+def test_network_parity_over_hundreds_of_steps(G):
+    """A network of uneven transmissive segments (3 .. 300 cells) advanced 300
+    of each segment's own steps: every segment within the t_end bar of the
+    single-domain oracle."""
+    net = network_case(24, seed=11, nmax=300)
+    S = len(net.n_cells)
+    c = oracle_cfg(oracle.EULER, 3, oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 300)
+    sim = _gpu_sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                   G.GRPREC_BC_TRANSMISSIVE, schedule=G.GRPREC_SCHED_FLAT_TILES, block=64)
+    try:
+        print("network, 300 steps", flush=True)
+        steps, _ = sim.run(1e9, 300)
+        assert steps == 300
+        qg, vg, _, _ = sim.numpy_state()
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-12)
+    finally:
+        sim.close()
+    for s in range(S):
+        c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s

@@ -307,3 +307,39 @@ def test_sod_with_grprecnl_under_these_readings():
         with pytest.raises(oracle.OracleError) as ei:
             oracle.run(c, dx, q, v, 0.0, 0.2, max_steps=10)
         assert ei.value.code in (oracle.E_PREDICTOR, oracle.E_NONPHYSICAL)
+
+
+# The paper's Riemann problems (Sec. 4.3.2, its table of Riemann data): Sod with
+# the jump at x_c = 0.3, t = 0.2, C_CFL 0.9; the 123 problem at t = 0.15 with
+# C_CFL 0.9 at orders 2-3 and 0.7 at orders 4-5.
+PAPER_RP = {
+    "sod": ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.3, 0.2),
+    "123": ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.5, 0.15),
+}
+
+
+@pytest.mark.parametrize("name", ["sod", "123"])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_paper_riemann_problems_fail_under_every_reading(name, order):
+    """The paper runs these with GRPrecNL; here, with lambda_C = 1e9 or 10,
+    the exact or the two-rarefaction interface datum (Sec. 4.1, also for the
+    first-step data), they stop within the first three steps with a
+    predictor that does not converge or a non-physical state.  Beside Sod's
+    jump the GRPrecNL weights of the acoustic fields pick the candidate whose
+    velocity spans the star state and the low-pressure side; there the local
+    |u| + c of the reconstruction exceeds S_max of the averages (Sec. 4.1) by
+    up to 40 %, so the predictor's local Courant number passes 1: its Picard
+    iteration diverges, and the fixed point itself (found by Newton) has a
+    negative pressure.  Other first-step data at the jump (the mean of the two
+    limits, either limit) fail the same way."""
+    left, right, xc, t_end = PAPER_RP[name]
+    cfl = 0.7 if (name == "123" and order >= 4) else 0.9
+    dx, q, vl, vr = I.euler_shock_tube(100, left=left, right=right, xc=xc)
+    for lam_c in (oracle.LAMBDA_C_PRINTED, oracle.LAMBDA_C_TABLE):
+        for datum in (oracle.DATUM_EXACT, oracle.DATUM_TRRS):
+            c = oracle.cfg(oracle.EULER, order, cfl=cfl, bc=oracle.TRANSMISSIVE, recon=oracle.NONLINEAR,
+                           nl_lambda_c=lam_c, datum=datum)
+            v = oracle.init_interfaces(c, vl, vr)
+            with pytest.raises(oracle.OracleError) as ei:
+                oracle.run(c, dx, q, v, 0.0, t_end, max_steps=3)
+            assert ei.value.code in (oracle.E_PREDICTOR, oracle.E_NONPHYSICAL), (lam_c, datum)
