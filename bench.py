@@ -152,15 +152,25 @@ def bench_network(args, G, torch, params):
                               params, sched, block)
     out["flops_per_step"] = fl
     out["iterations"] = it
+    out["batched_mlp"]["learned_starts_per_step"] = it["mlp_guesses_per_step"]
+    out["batched_mlp"]["learned_start_note"] = (
+        "the learned start is taken only at interfaces whose first Riemann problem jumps by more than"
+        " the gate (0.1); on this smooth network that happens %g times per step, so this form runs the"
+        " PVRS start's arithmetic; the tube network measures what the learned start gains"
+        % it["mlp_guesses_per_step"])
     out["net"] = net
     return out
 
 
-def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0):
+LAMBDA_C_PRINTED = 1e9   # GRPrecNL lambda_C as Sec. 3.3 prints it
+LAMBDA_C_TABLE = 10.0    # the value that reproduces the printed GRPrecNL advection table
+
+
+def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0, nl_lambda_c=LAMBDA_C_PRINTED):
     from paper_2602_21911_amd import inputs as I
     dx, q, vl, vr = I.adv_sin2pi(n)
     sim = G.Simulation(G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC,
-                       recon=recon)
+                       recon=recon, nl_lambda_c=nl_lambda_c)
     try:
         sim.run(1e9, warmup)
         sec, _ = timed_run(sim, steps, torch)
@@ -170,9 +180,21 @@ def bench_advection(G, torch, n, order=3, steps=200, warmup=20, recon=0):
     gbs = BYTES_ADV * n / per / 1e9
     key = "adv_step_order%d_2e25%s" % (order, "_nl" if recon else "")
     traffic = traffic_from_profiles(key, n) if n == 1 << 25 else None
-    return {"cells": n, "order": order, "recon": "GRPrecNL" if recon else "GRPrec", "rate": n / per,
-            "ms_per_step": 1e3 * per, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm",
-            "traffic": traffic}
+    out = {"cells": n, "order": order, "recon": "GRPrecNL" if recon else "GRPrec", "rate": n / per,
+           "ms_per_step": 1e3 * per, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm",
+           "traffic": traffic}
+    if recon:
+        out["nl_lambda_c"] = nl_lambda_c
+    return out
+
+
+def advection_lines(G, torch):
+    """Advection of sin 2 pi x (periodic, CFL 0.9): GRPrec orders 2-5 at 2^20,
+    2^22 and 2^25 cells (the last beyond the 256 MB last-level cache), and
+    GRPrecNL orders 3 and 5 at 2^25."""
+    out = [bench_advection(G, torch, n, order=o) for o in (2, 3, 4, 5) for n in (1 << 20, 1 << 22, 1 << 25)]
+    out += [bench_advection(G, torch, 1 << 25, order=o, recon=1) for o in (3, 5)]
+    return out
 
 
 def bench_small_case(G, torch, I, cfl=0.9):
@@ -212,12 +234,13 @@ def bench_small_case(G, torch, I, cfl=0.9):
     return out
 
 
-def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon, datum=0):
+def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon, datum=0,
+                  nl_lambda_c=LAMBDA_C_PRINTED):
     """Rate of one batched form, and its solver counters over the same steps
     (counted in a second, untimed run)."""
     cells = int(net.n_cells.sum())
     kw = dict(bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params, schedule=schedule,
-              block=block, recon=recon, datum=datum)
+              block=block, recon=recon, datum=datum, nl_lambda_c=nl_lambda_c)
     sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr, **kw)
     try:
         sched, blk = G.grprec_get_schedule(sim.h)
@@ -234,30 +257,45 @@ def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, 
     finally:
         sim.close()
     rs = max(1, st["rs_calls"])
-    return {"rate": cells * steps / sec, "ms_per_step": 1e3 * sec / steps, "schedule": sched,
-            "block": blk, "newton_per_rs": st["newton_iters"] / rs,
-            "mlp_starts_per_rs": st["mlp_guesses"] / rs,
-            "sweeps_per_cell": st["picard_sweeps"] / max(1, st["cells_predicted"])}
+    k = warmup + steps
+    out = {"rate": cells * steps / sec, "ms_per_step": 1e3 * sec / steps, "schedule": sched,
+           "block": blk, "newton_per_rs": st["newton_iters"] / rs,
+           "mlp_starts_per_rs": st["mlp_guesses"] / rs,
+           "newton_iters_per_step": st["newton_iters"] / k, "learned_starts_per_step": st["mlp_guesses"] / k,
+           "sweeps_per_cell": st["picard_sweeps"] / max(1, st["cells_predicted"])}
+    if recon:
+        out["nl_lambda_c"] = nl_lambda_c
+    return out
 
 
 def bench_tube_network(G, torch, params, steps=100, warmup=10):
     """10^4 shock tubes (GRPrecNL, order 3): the discontinuous workload on
     which the learned Newton start can matter; PVRS vs learned start, same
-    schedule."""
+    schedule.  GRPrecNL runs with lambda_C = 10: the tube family was chosen as
+    the strength GRPrecNL carries with it; with the printed 1e9 GRPrecNL is
+    GRPrec on most cells and these tubes fail (non-physical states)."""
     from paper_2602_21911_amd import inputs as I
     net = I.tube_network(n_seg=10000, seed=I.SEED_TUBE_NETWORK)
-    out = {"workload": "10000 shock tubes, GRPrecNL order 3, cells uniform [20,200) (seed %d), rho and p"
-                       " ratios up to 2, |u| <= 0.1, transmissive" % I.SEED_TUBE_NETWORK,
-           "cells": int(net.n_cells.sum())}
+    lam = LAMBDA_C_TABLE
+    out = {"workload": "10000 shock tubes, GRPrecNL order 3 (lambda_C %g), cells uniform [20,200) (seed"
+                       " %d), rho and p ratios up to 2, |u| <= 0.1, transmissive" % (lam, I.SEED_TUBE_NETWORK),
+           "cells": int(net.n_cells.sum()), "nl_lambda_c": lam}
     first = G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS
-    a = _network_form(G, torch, net, first, params, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1)
+    a = _network_form(G, torch, net, first, params, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1,
+                      nl_lambda_c=lam)
     out["batched_mlp" if params is not None else "batched_pvrs"] = a
     if params is not None:
         out["batched_pvrs"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, a["schedule"],
-                                            a["block"], steps, warmup, 1)
+                                            a["block"], steps, warmup, 1, nl_lambda_c=lam)
     out["batched_pvrs_trrs_datum"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None,
                                                    a["schedule"], a["block"], steps, warmup, 1,
-                                                   G.GRPREC_DATUM_TRRS)
+                                                   G.GRPREC_DATUM_TRRS, nl_lambda_c=lam)
+    if params is not None:
+        # Newton iterations the learned start saves per step (same steps, same
+        # schedule), and how many learned starts were taken
+        out["newton_iters_saved_per_step"] = (out["batched_pvrs"]["newton_iters_per_step"]
+                                              - a["newton_iters_per_step"])
+        out["learned_starts_per_step"] = a["learned_starts_per_step"]
     return out
 
 
@@ -268,7 +306,10 @@ def bench_network_variants(G, torch, steps=100, warmup=10):
     net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
     out = {"cells": int(net.n_cells.sum())}
     out["grprecnl"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0,
-                                    steps, warmup, 1)
+                                    steps, warmup, 1, nl_lambda_c=LAMBDA_C_PRINTED)
+    out["grprecnl_lambda_c_10"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None,
+                                                G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1,
+                                                nl_lambda_c=LAMBDA_C_TABLE)
     out["trrs_datum"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_AUTO, 0,
                                       steps, warmup, 0, G.GRPREC_DATUM_TRRS)
     return out
@@ -285,8 +326,9 @@ def bench_euler_single(G, torch, n, order=3, steps=50, warmup=5):
     finally:
         sim.close()
     per = sec / steps
-    return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per,
-            "hbm_gbs": BYTES_EULER * n / per / 1e9}
+    gbs = BYTES_EULER * n / per / 1e9
+    return {"cells": n, "order": order, "rate": n / per, "ms_per_step": 1e3 * per, "hbm_gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS}
 
 
 def cpu_baseline(net, steps: int):
@@ -378,6 +420,25 @@ def counters_run(G, torch, I):
                       "advection_cells": 1 << 25, "copy_bytes": a.numel() * 8}), flush=True)
 
 
+def trace_run(args, G, torch, I, learn):
+    """The headline form (batched, learned start) on a fixed schedule: W warm-up
+    and K timed steps, so a kernel trace's launches of the step kernel are
+    exactly these steps."""
+    ds = learn.build_dataset(args.train_n)
+    P, _ = learn.train(ds, epochs=args.epochs)
+    net = I.network(n_seg=args.segments, seed=I.SEED_NETWORK)
+    cells = int(net.n_cells.sum())
+    sim = make_network(G, net, G.GRPREC_GUESS_MLP, P, args.schedule, args.block)
+    try:
+        sim.run(1e9, args.warmup)
+        sec, _ = timed_run(sim, args.steps, torch)
+    finally:
+        sim.close()
+    print(json.dumps({"trace_run": "done", "cells": cells, "schedule": args.schedule, "block": args.block,
+                      "warmup": args.warmup, "steps": args.steps, "ms_per_step": 1e3 * sec / args.steps,
+                      "rate": cells * args.steps / sec}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,9 +452,14 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip advection / single-domain lines")
-    ap.add_argument("--only", choices=["all", "advection", "counters"], default="all",
+    ap.add_argument("--only", choices=["all", "advection", "counters", "trace"], default="all",
                     help="advection: only the advection lines; counters: a short fixed run for"
-                         " hardware-counter passes (network, advection 2^25, a 256 MB copy)")
+                         " hardware-counter passes (network, advection 2^25, a 256 MB copy);"
+                         " trace: the headline network form on a fixed schedule (--schedule,"
+                         " --block; no autotuning), W + K steps, for a kernel trace whose every"
+                         " launch of the step kernel is a warm-up or timed step")
+    ap.add_argument("--schedule", type=int, default=2, help="tile schedule of --only trace")
+    ap.add_argument("--block", type=int, default=64, help="workgroup size of --only trace")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -411,14 +477,14 @@ def main():
     torch.cuda.set_device(0)
     G.lib()
     if args.only == "advection":
-        out = [bench_advection(G, torch, 1 << 22), bench_advection(G, torch, 1 << 25),
-               bench_advection(G, torch, 1 << 25, order=5),
-               bench_advection(G, torch, 1 << 25, recon=1),
-               bench_advection(G, torch, 1 << 25, order=5, recon=1)]
+        out = advection_lines(G, torch)
         print(json.dumps({"advection": out}), flush=True)
         return
     if args.only == "counters":
         counters_run(G, torch, I)
+        return
+    if args.only == "trace":
+        trace_run(args, G, torch, I, learn)
         return
 
     params = None
@@ -471,12 +537,9 @@ def main():
     if mlp is not None:
         line["mlp"] = mlp
     if not args.no_extras:
-        line["advection"] = [bench_advection(G, torch, 1 << 20), bench_advection(G, torch, 1 << 22),
-                             bench_advection(G, torch, 1 << 25),
-                             bench_advection(G, torch, 1 << 25, order=5),
-                             bench_advection(G, torch, 1 << 25, recon=1),
-                             bench_advection(G, torch, 1 << 25, order=5, recon=1)]
-        line["euler_single_domain"] = bench_euler_single(G, torch, 1 << 22)
+        line["advection"] = advection_lines(G, torch)
+        line["euler_single_domain"] = [bench_euler_single(G, torch, n, order=o)
+                                       for o in (2, 3, 4) for n in (1 << 20, 1 << 22)]
         line["network_variants"] = bench_network_variants(G, torch)
         line["tube_network"] = bench_tube_network(G, torch, params)
         line["small_case"] = bench_small_case(G, torch, I)
