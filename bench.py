@@ -390,9 +390,9 @@ def cpu_all_cores(net, steps: int):
 
 def counters_run(G, torch, I):
     """Short fixed workload for rocprofv3 --pmc passes: 3 network steps (flat
-    tiles, 64-wide blocks), 3 advection steps on 2^25 cells for GRPrec order 3
-    and 5 and GRPrecNL order 3, and a 256 MiB device copy used to calibrate
-    the byte counters."""
+    tiles, 64-wide blocks), 3 advection steps on 2^25 cells for GRPrec orders
+    2-5 and GRPrecNL orders 3 and 5, and a 256 MiB device copy used to
+    calibrate the byte counters."""
     net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
     sim = make_network(G, net, G.GRPREC_GUESS_PVRS, None, G.GRPREC_SCHED_FLAT_TILES, 64)
     try:
@@ -402,7 +402,7 @@ def counters_run(G, torch, I):
     finally:
         sim.close()
     dx, q, vl, vr = I.adv_sin2pi(1 << 25)
-    for order, recon in ((3, 0), (5, 0), (3, 1)):
+    for order, recon in ((2, 0), (3, 0), (4, 0), (5, 0), (3, 1), (5, 1)):
         sim = G.Simulation(G.GRPREC_ADVECTION, order, [1 << 25], [1.0], q, vl, vr,
                            bc=G.GRPREC_BC_PERIODIC, recon=recon)
         try:
