@@ -28,6 +28,55 @@ namespace grp {
 #define GRPREC_EULER_WAVES(M) ((M) <= 2 ? 2 : 1)
 #endif
 
+// g = D f, the derivative at the nodes of the interpolant of nodal values f,
+// through the even and odd parts of f about the centre (tab::Predictor's
+// De, Do, Dm, Dc): 7 operations instead of 9 at N = 3, 20 instead of 25 at
+// N = 5.  With the row sums of D zero, the even part's coefficients of one row
+// sum to zero, which removes one term for even N (all of it at N = 2).
+template <int N, class Tab>
+__device__ __forceinline__ void deriv_sym(const Tab &T, const double (&f)[N], double (&g)[N]) {
+  constexpr int H = N / 2;
+  double s[H], d[H];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    s[k] = f[k] + f[N - 1 - k];
+    d[k] = f[k] - f[N - 1 - k];
+  }
+#pragma unroll
+  for (int x = 0; x < H; ++x) {
+    double o = T.Do[x][0] * d[0];
+#pragma unroll
+    for (int k = 1; k < H; ++k) o = fma(T.Do[x][k], d[k], o);
+    if constexpr (N % 2 == 1) {
+      double e = T.Dm[x] * f[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) e = fma(T.De[x][k], s[k], e);
+      g[x] = o + e;
+      g[N - 1 - x] = o - e;
+    } else if constexpr (H > 1) {
+      double e = T.De[x][0] * (s[0] - s[H - 1]);
+#pragma unroll
+      for (int k = 1; k < H - 1; ++k) e = fma(T.De[x][k], s[k] - s[H - 1], e);
+      g[x] = o + e;
+      g[N - 1 - x] = o - e;
+    } else {
+      g[x] = o;
+      g[N - 1 - x] = o;
+    }
+  }
+  if constexpr (N % 2 == 1) {
+    double c = T.Dc[0] * d[0];
+#pragma unroll
+    for (int k = 1; k < H; ++k) c = fma(T.Dc[k], d[k], c);
+    g[H] = c;
+  }
+}
+
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
+
 // AIR: gamma is 1.4 and the gas constants are compile-time values.
 // NL: GRPrecNL reconstruction (Sec. 3.3-3.4) instead of GRPrec (Sec. 3.1).
 // TR: end-of-step datum by the two-rarefaction solver (Sec. 4.1); a run-time
@@ -294,27 +343,29 @@ void euler_step(EulerArgs<M> a) {
         for (int x = 0; x < N; ++x) euler_flux(G, w[0][x], w[1][x], w[2][x], F1[0][x], F1[1][x], F1[2][x]);
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
+          double Gd[N];
+          deriv_sym<N>(T, F1[v], Gd);
 #pragma unroll
           for (int x = 0; x < N; ++x) {
-            double Gd = 0.0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) Gd += T.D[x][k] * F1[v][k];
+            const double t = nu * Gd[x];
 #pragma unroll
             for (int b = 0; b < N; ++b) {
               if constexpr (SRC) {
                 double rs = 0.0;
 #pragma unroll
                 for (int l = 0; l < N; ++l) rs += SA[b][l];
-                qh[v][x][b] = gf[b] * w[v][x] - nu * (rs * Gd);
+                qh[v][x][b] = fma(-rs, t, gf[b] * w[v][x]);
               } else {
-                qh[v][x][b] = w[v][x] - nu * (T.KWs[b] * Gd);
+                qh[v][x][b] = fma(-T.KWs[b], t, w[v][x]);
               }
             }
           }
         }
       }
-      // One sweep from qa into qb; true when its change meets the tolerance.
-      auto sweep = [&](const double (&qa)[3][N][N], double (&qb)[3][N][N]) -> bool {
+      // One sweep from qa into qb; with TEST, true when its change meets the
+      // tolerance (without, the change is not formed).
+      auto sweep = [&](const double (&qa)[3][N][N], double (&qb)[3][N][N], auto test) -> bool {
+        constexpr bool TEST = decltype(test)::value;
         double F[3][N][N];
 #pragma unroll
         for (int x = 0; x < N; ++x)
@@ -324,38 +375,42 @@ void euler_step(EulerArgs<M> a) {
         double diff = 0.0, nrm = 0.0;
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
+          double Gd[N][N];  // [x][l]: space derivative at node x, time node l
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            double f[N], g[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) f[k] = F[v][k][l];
+            deriv_sym<N>(T, f, g);
+#pragma unroll
+            for (int x = 0; x < N; ++x) Gd[x][l] = g[x];
+          }
 #pragma unroll
           for (int x = 0; x < N; ++x) {
-            double Gd[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-              double acc = 0.0;
-#pragma unroll
-              for (int k = 0; k < N; ++k) acc += T.D[x][k] * F[v][k][l];
-              Gd[l] = acc;
-            }
 #pragma unroll
             for (int b = 0; b < N; ++b) {
               double acc = 0.0;
               double wb = w[v][x];
               if constexpr (SRC) {
 #pragma unroll
-                for (int l = 0; l < N; ++l) acc += SA[b][l] * Gd[l];
+                for (int l = 0; l < N; ++l) acc += SA[b][l] * Gd[x][l];
                 wb *= gf[b];
               } else {
 #pragma unroll
-                for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[l];
+                for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[x][l];
               }
               const double nv = wb - nu * acc;
               // non-finite values do not stop the sweep here: they reach the
               // traces and are caught by the physical-state checks
-              diff = fmax(diff, fabs(nv - qa[v][x][b]));
-              nrm = fmax(nrm, fabs(nv));
+              if constexpr (TEST) {
+                diff = fmax(diff, fabs(nv - qa[v][x][b]));
+                nrm = fmax(nrm, fabs(nv));
+              }
               qb[v][x][b] = nv;
             }
           }
         }
-        return diff <= a.picard_tol * (1.0 + nrm);
+        return TEST && diff <= a.picard_tol * (1.0 + nrm);
       };
       // Later sweeps alternate between qh and qt (no register copies per
       // sweep); the iterate ends in qh.
@@ -376,13 +431,22 @@ void euler_step(EulerArgs<M> a) {
       }
       {
         double qt[3][N][N];
-        while (it < a.max_picard) {
+        if (N >= 3 && a.max_picard >= 3) {
+          // The second sweep's change is not tested either: where it would
+          // meet the tolerance the iteration has converged, the third sweep
+          // changes the iterate by less again, and only the sweep count
+          // differs from stopping at the second.
+          sweep(qh, qt, Flag<false>{});
+          conv = sweep(qt, qh, Flag<true>{});
+          it = 3;
+        }
+        while (!conv && it < a.max_picard) {
           ++it;
-          if (sweep(qh, qt)) {
+          if (sweep(qh, qt, Flag<true>{})) {
             conv = true;
           } else if (it < a.max_picard) {
             ++it;
-            conv = sweep(qt, qh);
+            conv = sweep(qt, qh, Flag<true>{});
             if (!conv) continue;
             break;
           }

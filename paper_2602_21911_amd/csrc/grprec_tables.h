@@ -96,6 +96,12 @@ struct Predictor {
   double KWs[N];     // row sums of KW (the time solve of a time-constant argument)
   double l0[N], l1[N];
   double phi[N][4];  // xi, xi^2 - 1/12, xi^3, xi^4 - 1/80 at xi = g_a - 1/2
+  // D split by the nodes' symmetry about 1/2, D[N-1-a][N-1-k] = -D[a][k]
+  // (H = N/2): for a, k < H, De[a][k] = (D[a][k] + D[a][N-1-k]) / 2 acts on
+  // the even part f_k + f_{N-1-k} and Do[a][k] = (D[a][k] - D[a][N-1-k]) / 2
+  // on the odd part f_k - f_{N-1-k}; for odd N, Dm[a] = D[a][H] and the
+  // middle row Dc[k] = D[H][k] (odd, so D[H][H] = 0).
+  double De[N / 2][N / 2], Do[N / 2][N / 2], Dm[N / 2], Dc[N / 2];
 };
 
 template <int M>
@@ -146,6 +152,14 @@ constexpr Predictor<M> predictor() {
     P.phi[a][1] = x2 - 1.0 / 12.0;
     P.phi[a][2] = x2 * xi;
     P.phi[a][3] = x2 * x2 - 1.0 / 80.0;
+  }
+  for (int a = 0; a < N / 2; ++a) {
+    for (int k = 0; k < N / 2; ++k) {
+      P.De[a][k] = 0.5 * (P.D[a][k] + P.D[a][N - 1 - k]);
+      P.Do[a][k] = 0.5 * (P.D[a][k] - P.D[a][N - 1 - k]);
+      P.Dc[k] = P.D[N / 2][k];
+    }
+    P.Dm[a] = P.D[a][N / 2];
   }
   return P;
 }
