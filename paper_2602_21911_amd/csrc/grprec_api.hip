@@ -65,7 +65,9 @@ static Layout layout(const grprec_problem *p, long long tc) {
   L.dx = o; o = align256(o + sizeof(double) * S);
   L.t = o; o = align256(o + sizeof(double) * 3 * S);
   L.smax = o; o = align256(o + sizeof(unsigned long long) * 3 * S);
-  L.max_tiles = (p->system == GRPREC_EULER) ? tc / 62 + S + 2 : 0;
+  // tiles of at least 62 slots over the cells and, when transmissive, one
+  // ghost slot per domain
+  L.max_tiles = (p->system == GRPREC_EULER) ? (tc + S) / 62 + S + 2 : 0;
   L.tiles = o; o = align256(o + sizeof(Tile) * L.max_tiles);
   L.src = o; o = align256(o + sizeof(double) * 3 * 5);  // advection's per-step source maps
   L.snap_doubles = (p->system == GRPREC_EULER && p->schedule == GRPREC_SCHED_AUTO)
@@ -141,7 +143,13 @@ static std::vector<Tile> build_tiles(grprec_handle *h, int schedule, int block) 
   // the per-domain launches use segment tiles
   const int order = (schedule == GRPREC_SCHED_FLAT_TILES || schedule == GRPREC_SCHED_PACKED)
                         ? schedule : (int)kSegmentTiles;
-  return plan_tiles(h->cell_off, order, block, h->p.bc == GRPREC_BC_PERIODIC, h->dom_tile0);
+  const bool periodic = h->p.bc == GRPREC_BC_PERIODIC;
+  if (periodic) return plan_tiles(h->cell_off, order, block, true, h->dom_tile0);
+  // transmissive: slots are each domain's ghost slot followed by its cells,
+  // so domain s spans slots off[s] + s .. off[s + 1] + s
+  std::vector<int> xoff(h->cell_off.size());
+  for (size_t s = 0; s < xoff.size(); ++s) xoff[s] = h->cell_off[s] + (int)s;
+  return plan_tiles(xoff, order, block, false, h->dom_tile0);
 }
 
 static int euler_occ(int M, int block, bool nl, int *occ) {

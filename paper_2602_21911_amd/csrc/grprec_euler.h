@@ -161,24 +161,31 @@ void euler_step(EulerArgs<M> a) {
     const LaneTile td = nx;
     if (tile + t_step < t_last) nx = lane_tile(tile + t_step);
     const int start = td.start, count = td.count;
-    // ---- which cell this slot holds, and its domain
-    bool valid = false, useful = false;
-    int c = 0;
+    // ---- which slot this lane holds, and its domain.  Periodic runs (one
+    // domain) index slots by cell.  Transmissive runs index them over each
+    // domain's cells preceded by a ghost slot (slot off[s] + s of domain s,
+    // the index of the domain's left interface), which solves the Riemann
+    // problems of the left end like any interior slot solves those of its
+    // right interface.
+    bool valid = false, owned = false;
+    int x = 0;
     if (e >= 1 && e <= count) {
-      c = start + e - 1;
-      valid = useful = true;
+      x = start + e - 1;
+      valid = owned = true;
     } else if (e == 0) {
-      c = td.cl;
-      valid = c >= 0;
+      x = td.cl;
+      valid = x >= 0;
     } else if (e == count + 1) {
-      c = td.cr;
-      valid = c >= 0;
+      x = td.cr;
+      valid = x >= 0;
     }
     const int s = (e == count + 1) ? td.w : td.base + __popcll(td.first & ((2ull << (e & 63)) - 1ull));
-    // every read of the slot depends on (c, s) alone, so they are issued together
+    // every read of the slot depends on (x, s) alone, so they are issued
+    // together; a ghost slot reads (and ignores) a neighbouring cell's data
+    const int c = a.periodic ? x : max(x - s - 1, 0);
     int off = 0, n = 1, i = 0, io = 0;
     double dx = 1.0, dt = 0.0, t_new = 0.0, nu = 0.0, t = 0.0;
-    bool done = true;
+    bool done = true, ghost = false;
     double q0[3], vl0[3], vr0[3];
     if (valid) {
       off = a.seg.cell_off[s];
@@ -192,11 +199,13 @@ void euler_step(EulerArgs<M> a) {
         vl0[v] = vin[v * ti + c + s];
         vr0[v] = vin[v * ti + c + s + 1];
       }
-      i = c - off;
+      ghost = !a.periodic && x == off + s;
+      i = ghost ? -1 : c - off;
       io = off + s;
       domain_dt(a.cfl, dx, S, t, t_end, dt, t_new, done);
       nu = dt / dx;
     }
+    const bool useful = owned && !ghost;
     const bool work = valid && !done;
     // implicit source: the predictor's time matrices for this slot's dt, and
     // the factors of the constant-state evolution (ghost cells): gf[b] at the
@@ -224,7 +233,7 @@ void euler_step(EulerArgs<M> a) {
 
     // ---- reconstruct, predict
     double src_dt[3] = {0.0, 0.0, 0.0};
-    if (work) {
+    if (work && !ghost) {
       int im = i - 1, ip = i + 1;
       if (a.periodic) {
         if (im < 0) im += n;
@@ -476,7 +485,8 @@ void euler_step(EulerArgs<M> a) {
         }
       }
       st_cells += 1;
-      // traces at xi = 0 and xi = 1, times g_b and 1, staged in LDS
+      // traces at xi = 0 and xi = 1, times g_b and 1 (the latter from the
+      // former: evaluation in space and in time commute), staged in LDS
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         double l1sum = 0.0, r1sum = 0.0;
@@ -490,17 +500,22 @@ void euler_step(EulerArgs<M> a) {
           }
           sTL[v * NT + b][e] = l;
           sTR[v * NT + b][e] = r;
-        }
-#pragma unroll
-        for (int x = 0; x < N; ++x) {
-          double at1 = 0.0;
-#pragma unroll
-          for (int b = 0; b < N; ++b) at1 += T.l1[b] * qh[v][x][b];
-          l1sum += T.l0[x] * at1;
-          r1sum += T.l1[x] * at1;
+          l1sum = fma(T.l1[b], l, l1sum);
+          r1sum = fma(T.l1[b], r, r1sum);
         }
         sTL[v * NT + N][e] = l1sum;
         sTR[v * NT + N][e] = r1sum;
+      }
+      // a domain's first cell gives its ghost slot the ghost state, the end
+      // average (constant, or decaying with the source) at the trace times
+      if (!a.periodic && i == 0 && e >= 1) {
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+          double f = 1.0;
+          if constexpr (SRC) f = pick<N + 1>(gf, b);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) sTR[v * NT + b][e - 1] = f * q0[v];
+        }
       }
     }
     __syncthreads();
@@ -509,8 +524,8 @@ void euler_step(EulerArgs<M> a) {
     // transmissive end the outside data are a ghost cell holding the end
     // cell's average, constant in space and time.
     double FR[3] = {0.0, 0.0, 0.0}, VR[3] = {0.0, 0.0, 0.0};
-    const bool rs_lane = work && (useful || e == 0);
-    const bool boundary = (!a.periodic) && (i == n - 1);
+    const bool rs_lane = work && (useful || ghost || e == 0);
+    const bool boundary = (!a.periodic) && (i == n - 1);  // false for ghost slots (i = -1)
     const bool gated = a.warm || a.guess == 1;
     // data of the Riemann problem at trace time b: this slot's right trace
     // against the right neighbour's left trace (or the ghost state)
@@ -634,46 +649,7 @@ void euler_step(EulerArgs<M> a) {
         sTR[3 + v][e] = VR[v];
       }
     }
-    // left end of a transmissive domain: ghost average against the left trace
-    // (above the gate the later times start from the first time's star
-    // pressure; the learned start is taken at interior and right-end
-    // interfaces only)
     double FL[3] = {0.0, 0.0, 0.0}, VL[3] = {0.0, 0.0, 0.0};
-    if (work && useful && i == 0 && !a.periodic) {
-      double pw = 0.0;
-      bool strong = false;
-#pragma unroll 1
-      for (int b = 0; b < NT; ++b) {
-        double QR[3] = {sTL[0 * NT + b][e], sTL[1 * NT + b][e], sTL[2 * NT + b][e]};
-        double QG[3] = {q0[0], q0[1], q0[2]};  // the ghost's state at this time
-        if constexpr (SRC) {
-          const double f = pick<N + 1>(gf, b);
-          QG[0] *= f; QG[1] *= f; QG[2] *= f;
-        }
-        RSOut o;
-        if (TR && b == N)  // end-of-step datum by the two-rarefaction solver
-          err |= trrs_interact(G, QG, QR, o);
-        else if (bool above_l; !((b == 0 || !strong) &&
-                                 weak_interact(G, QG, QR, a.newton_tol, b == 0 && gated, a.gate, o, above_l)))
-          err |= interact(G, QG, QR, (b > 0 && strong) ? pw : 0.0, a.max_newton, a.newton_tol, o,
-                          nullptr, a.gate, b == 0 && gated);
-        if (b == 0) {  // later times start from the first time's p* above the gate
-          strong = o.strong;
-          pw = o.pstar;
-        }
-        st_mlp += o.learned ? 1 : 0;
-        st_rs += 1;
-        st_newton += o.iters;
-        if (b < N) {
-          const double wb = pick<N>(T.w, b);
-#pragma unroll
-          for (int v = 0; v < 3; ++v) FL[v] += wb * o.F[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) VL[v] = o.Q[v];
-        }
-      }
-    }
     __syncthreads();
 
     // ---- conservative update and S_max of the new state
@@ -682,12 +658,12 @@ void euler_step(EulerArgs<M> a) {
     if (useful) {
       double qn[3];
       if (work) {
-        if (i > 0 || a.periodic) {
+        // the left interface's flux and datum: the left neighbour's, the
+        // ghost slot's at a domain's left end
 #pragma unroll
-          for (int v = 0; v < 3; ++v) {
-            FL[v] = sTR[v][e - 1];
-            VL[v] = sTR[3 + v][e - 1];
-          }
+        for (int v = 0; v < 3; ++v) {
+          FL[v] = sTR[v][e - 1];
+          VL[v] = sTR[3 + v][e - 1];
         }
 #pragma unroll
         for (int v = 0; v < 3; ++v) qn[v] = q0[v] - nu * (FR[v] - FL[v]);
