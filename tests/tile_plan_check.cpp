@@ -1,9 +1,13 @@
 // Checks the batched Euler step's tile plans on the host: for random domain
 // layouts, every tile order and block width, and both boundary kinds, every
-// slot's cell and domain as the kernel derives them from the descriptor must
-// equal the brute-force answer, the owned cells must cover all cells once in
-// order, and each order must keep its own rule.  Prints "ok <slots>" or the
-// first failures; the exit status is the number of failures (capped).
+// slot's index and domain as the kernel derives them from the descriptor must
+// equal the brute-force answer, the owned slots must cover all slots once in
+// order, and each order must keep its own rule.  Periodic plans index slots by
+// cell; transmissive plans, as the library builds them, index each domain's
+// ghost slot followed by its cells (domain s spans off[s] + s .. off[s+1] + s),
+// and the kernel's cell and ghost derivation must hold too, with every
+// domain's first cell next to its ghost in the same tile.  Prints "ok <slots>"
+// or the first failures; the exit status is the number of failures (capped).
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -30,14 +34,20 @@ int main() {
     std::vector<int> off(S + 1, 0);
     for (int s = 0; s < S; ++s) {
       // short domains (2..6 cells) in some layouts, else up to 600 cells
-      const int n = (trial % 3 == 0) ? 2 + int(rng() % 5) : 2 + int(rng() % 599);
+      // short domains (1..6 cells) in some layouts, else up to 600 cells
+      const int n = (trial % 3 == 0) ? 1 + int(rng() % 6) : 2 + int(rng() % 599);
       off[s + 1] = off[s] + n;
     }
     const bool periodic = trial % 2 == 0;
+    std::vector<int> xoff(S + 1);
+    for (int s = 0; s <= S; ++s) xoff[s] = off[s] + (periodic ? 0 : s);
+    const std::vector<int> cell_off = off;
     for (int order : {int(grp::kSegmentTiles), int(grp::kFlatTiles), int(grp::kPacked)}) {
       for (int block : {64, 128, 256}) {
         std::vector<int> dom_tile0;
+        const std::vector<int> &off = xoff;  // the slot offsets the plan is built on
         const std::vector<Tile> tiles = grp::plan_tiles(off, order, block, periodic, dom_tile0);
+        std::vector<int> ghost_slot(block, 0), cell_at(block, -2);
         int next_cell = 0;
         for (size_t k = 0; k < tiles.size(); ++k) {
           const Tile &d = tiles[k];
@@ -80,6 +90,8 @@ int main() {
               want_s = w;
               want_c = last + 1 < off[w + 1] ? last + 1 : (periodic ? off[w] : -1);
             }
+            cell_at[e] = -2;
+            ghost_slot[e] = 0;
             if (want_c < 0) {
               if (valid) fail("halo slot without a cell", trial, order, block, e);
               continue;
@@ -87,9 +99,30 @@ int main() {
             ++slots;
             if (!valid || c != want_c) fail("cell", trial, order, block, e);
             if (s != want_s || domain_of(off, c) != s) fail("domain", trial, order, block, e);
+            // the kernel's cell and ghost derivation from slot x = c and domain s
+            const int x = c;
+            const int cell = periodic ? x : (x - s - 1 > 0 ? x - s - 1 : 0);
+            const bool ghost = !periodic && x == cell_off[s] + s;
+            ghost_slot[e] = ghost;
+            cell_at[e] = ghost ? -1 : cell;
+            if (periodic && ghost) fail("ghost in a periodic plan", trial, order, block, e);
+            if (!ghost && (cell < cell_off[s] || cell >= cell_off[s + 1])) fail("cell outside its domain", trial, order, block, e);
+            if (!periodic && !ghost && x != cell + s + 1) fail("slot of a cell", trial, order, block, e);
+          }
+          // a domain's first cell (owned, or the right halo) has its ghost in
+          // the slot before; an owned ghost has its first cell in the slot after
+          if (!periodic) {
+            for (int e = 0; e < block; ++e) {
+              if (cell_at[e] >= 0 && e >= 1) {
+                const int s = domain_of(cell_off, cell_at[e]);
+                if (cell_at[e] == cell_off[s] && !ghost_slot[e - 1]) fail("first cell without its ghost", trial, order, block, e);
+              }
+              if (e >= 1 && e <= d.count && ghost_slot[e] && (e + 1 >= block || cell_at[e + 1] < 0))
+                fail("ghost without its first cell", trial, order, block, e);
+            }
           }
         }
-        if (next_cell != off[S]) fail("cells left over", trial, order, block, -1);
+        if (next_cell != off[S]) fail("slots left over", trial, order, block, -1);
         if (order == grp::kSegmentTiles) {
           if ((int)dom_tile0.size() != S + 1 || dom_tile0[S] != (int)tiles.size()) {
             fail("dom_tile0 size", trial, order, block, -1);
