@@ -55,9 +55,9 @@ def src_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, launch_units: float):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+def profile_record(kernel: str):
+    """The committed rocprofv3 counter record of a kernel, if it was taken on
+    the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -67,7 +67,14 @@ def traffic_from_profiles(kernel: str, launch_units: float):
         return None
     if not rec or rec.get("source_digest") != src_digest():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def traffic_from_profiles(kernel: str, launch_units: float):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    rec = profile_record(kernel)
+    return rec.get("hbm_bytes_per_launch") if rec else None
 
 
 def timed_run(sim, steps: int, torch):
@@ -511,6 +518,10 @@ def main():
     bytes_step = BYTES_EULER * cells + 48.0 * len(net.n_cells)
     achieved_tf = flops / sec_per_step / 1e12
     traffic = traffic_from_profiles("euler_step_order3", cells)
+    # FP64 flops the kernel executes (SQ_INSTS_VALU_FLOPS_FP64 of the committed
+    # counter runs, same sources), over this run's launch time
+    rec = profile_record("euler_step_order3") or {}
+    counted = rec.get("fp64_flops_per_launch_counted")
     roofline = {
         "kernel": "euler_step<M=2> (fused reconstruct + predictor + Riemann + update)",
         "bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -520,6 +531,9 @@ def main():
         "hbm_gbs": bytes_step / sec_per_step / 1e9,
         "hbm_frac": bytes_step / sec_per_step / 1e9 / PEAK_HBM_GBS,
         "iterations": res["iterations"],
+        "counted_fp64_flops_per_launch": counted,
+        "counted_tflops": counted / sec_per_step / 1e12 if counted else None,
+        "counted_frac": counted / sec_per_step / 1e12 / PEAK_FP64_TFLOPS if counted else None,
     }
     line = {
         "metric": METRIC, "value": head["rate"], "unit": "cell-updates/s", "n_gpus": 1,

@@ -131,7 +131,8 @@ typedef struct {
                           warm starts are taken; below it Newton starts from PVRS
                           (default 0.1; negative: always) */
   int warm_start;      /* 1: at interfaces above the gate, the later Riemann problems start
-                          from the first time's p* (implied by GUESS_MLP) */
+                          from the first time's p*, moved by the change of the PVRS
+                          estimate between the two problems (implied by GUESS_MLP) */
   int schedule;        /* GRPREC_SCHED_* (Euler) */
   int block;           /* workgroup size 64, 128 or 256 (0 = choose) */
   int recon;           /* GRPREC_RECON_* */

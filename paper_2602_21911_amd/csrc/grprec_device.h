@@ -15,28 +15,42 @@ __device__ __forceinline__ double bitsd(unsigned long long b) {
   return __longlong_as_double((long long)b);
 }
 
-// Largest of a and b, NaN wins (so a NaN reaches the error checks).
-__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
-
 // x^e for x > 0 as 2^(e log2 x): a few ulp, cheaper than a general pow.
 __device__ __forceinline__ double powpos(double x, double e) { return exp2(e * log2(x)); }
 
 // ---------------------------------------------------------------- reductions
-// Per-domain maximum over one wave: lanes hold (seg, val) with seg
-// non-decreasing over the lanes that take part (seg >= 0).  Returns true on
-// the first lane of each run of equal seg, which receives the run's maximum
-// as the bits of a non-negative double (bit patterns order like the values).
+// One step of the segmented scan below: the value of the lane selected by the
+// DPP control (the lane's own where there is none) is taken when it belongs to
+// the same run and is larger.  Values are the bit patterns of non-negative
+// doubles or NaN, which order as unsigned integers like the values, NaN
+// above all.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_max_step(int seg, unsigned long long &bits) {
+  const int lo = (int)bits, hi = (int)(bits >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+  const int os = __builtin_amdgcn_update_dpp(seg, seg, CTRL, ROW_MASK, 0xf, false);
+  const unsigned long long ob = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo;
+  if (os == seg && ob > bits) bits = ob;
+}
+
+// Per-domain maximum over one wave (every lane active): lanes hold (seg, val)
+// with each seg >= 0 on one contiguous run of lanes (lanes with seg < 0 take
+// no part), val >= 0 or NaN.  An inclusive segmented prefix maximum over the
+// lanes -- shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last
+// lane of rows 0 and 2 into rows 1 and 3, then the last lane of row 1 into
+// rows 2 and 3 -- leaves each run's maximum on its last lane, which returns
+// true and receives it as the bits of the double.
 __device__ __forceinline__ bool wave_segmented_lead(int seg, double val, unsigned long long &bits) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double ov = __shfl_down(val, d, 64);
-    int os = __shfl_down(seg, d, 64);
-    if (lane + d < 64 && os == seg) val = nanmax(val, ov);
-  }
-  const int prev = __shfl_up(seg, 1, 64);
   bits = dbits(val);
-  return seg >= 0 && (lane == 0 || prev != seg);
+  seg_max_step<0x111, 0xf>(seg, bits);  // row_shr:1
+  seg_max_step<0x112, 0xf>(seg, bits);  // row_shr:2
+  seg_max_step<0x114, 0xf>(seg, bits);  // row_shr:4
+  seg_max_step<0x118, 0xf>(seg, bits);  // row_shr:8
+  seg_max_step<0x142, 0xa>(seg, bits);  // row_bcast:15
+  seg_max_step<0x143, 0xc>(seg, bits);  // row_bcast:31
+  const int next = __builtin_amdgcn_update_dpp(seg, seg, 0x130, 0xf, 0xf, false);  // wave_shl:1
+  return seg >= 0 && ((threadIdx.x & 63) == 63 || next != seg);
 }
 
 // One atomicMax per run on base[seg].  The target only grows while it
@@ -490,6 +504,7 @@ struct RSOut {
   double F[3];
   double Q[3];
   double pstar;
+  double pv;    // PVRS estimate of the star pressure (general solver only)
   int iters;
   bool strong;  // the data jump passed the gate (when it was tested)
   bool learned; // Newton started from the learned proposal
@@ -499,17 +514,23 @@ struct RSOut {
 // test_gate the data jump is first tested against the gate (o.strong); below
 // the gate Newton starts from PVRS (already accurate to second order in the
 // jump for weak waves), above it from the learned proposal when
-// mlp != nullptr (o.learned), else from pguess when positive.
+// mlp != nullptr (o.learned), else from pguess when positive.  A warm start
+// pguess taken from another problem's star pressure comes with that
+// problem's PVRS estimate pv_ref > 0 and is moved by the difference of the
+// two problems' PVRS estimates: the error of PVRS varies smoothly with the
+// data, so the shifted start keeps only the change of that error between
+// the two problems.
 __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], const double QR[3],
                                              double pguess, int maxit, double tol, RSOut &o,
                                              const float *mlp = nullptr, double gate = 0.0,
-                                             bool test_gate = false) {
+                                             bool test_gate = false, double pv_ref = 0.0) {
   Prim L, R;
   bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
   bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
   o.iters = 0;
   o.strong = false;
   o.learned = false;
+  o.pv = 0.0;
   if (!(okl && okr)) {
     o.F[0] = o.F[1] = o.F[2] = 0.0;
     o.Q[0] = QL[0]; o.Q[1] = QL[1]; o.Q[2] = QL[2];
@@ -522,6 +543,8 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
     o.pstar = 0.0;
     return ERR_VACUUM;
   }
+  const double pv = pvrs(L, R);
+  o.pv = pv;
   double p0 = 0.0;
   if (test_gate) {
     o.strong = jump_exceeds(L, R, gate);
@@ -534,7 +557,8 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
   } else {
     p0 = pguess;
   }
-  if (!(p0 > 0.0)) p0 = pvrs(L, R);
+  if (p0 > 0.0 && pv_ref > 0.0) p0 += pv - pv_ref;
+  if (!(p0 > 0.0)) p0 = pv;
   double ps, us;
   Side sl, sr;
   int it = newton_pstar(G, L, R, p0, maxit, tol, ps, us, sl, sr);
@@ -588,7 +612,10 @@ __device__ __forceinline__ bool weak_prim(const Gas &G, double r, double m, doub
   y = y * fma(-0.5 * x * y, y, 1.5);
   w.irc = y;
   w.c = G.g * w.p * y;
-  return (r > 0.0) && (w.p > 0.0) && isfinite(w.u) && isfinite(w.p) && isfinite(w.c);
+  // physical and finite: with r > 0 and g p r a normal positive number, p > 0
+  // and u, c are finite (an infinite or NaN input drives p, hence g p r, to
+  // NaN, -inf or +inf); states near the range limits go to the general solver
+  return (r > 0.0) && (x > 1e-300) && (x < 1e300);
 }
 
 __device__ __forceinline__ bool weak_interact(const Gas &G, const double QL[3], const double QR[3], double tol,

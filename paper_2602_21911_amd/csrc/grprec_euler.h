@@ -623,12 +623,13 @@ void euler_step(EulerArgs<M> a) {
       } else {
         // General solver.  Above the gate the first time starts from the
         // learned proposal and the later times from the first time's star
-        // pressure; below it (and without gating) every time starts from PVRS.
+        // pressure, shifted by the change of the PVRS estimate; below it (and
+        // without gating) every time starts from PVRS.
         RSOut og;
         err |= interact(G, QL0, QR0, p_learn, a.max_newton, a.newton_tol, og, nullptr, a.gate, gated);
         og.learned = og.strong && p_learn > 0.0;
         take(0, og, QL0, QR0);
-        const double pg = og.strong ? og.pstar : 0.0;
+        const double pg = og.strong ? og.pstar : 0.0, pvg = og.strong ? og.pv : 0.0;
 #pragma unroll
         for (int b = 1; b < NT; ++b) {
           double QL[3], QR[3];
@@ -637,7 +638,7 @@ void euler_step(EulerArgs<M> a) {
           if (TR && b == N)
             err |= trrs_interact(G, QL, QR, o);
           else
-            err |= interact(G, QL, QR, pg, a.max_newton, a.newton_tol, o);
+            err |= interact(G, QL, QR, pg, a.max_newton, a.newton_tol, o, nullptr, 0.0, false, pvg);
           take(b, o, QL, QR);
         }
       }
