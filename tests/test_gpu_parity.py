@@ -311,3 +311,32 @@ def test_network_parity_over_hundreds_of_steps(G):
         c0, c1 = net.cell_off[s], net.cell_off[s + 1]
         assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
+
+
+@pytest.mark.parametrize("schedule,block", [(1, 64), (2, 64), (3, 128)])
+def test_network_segments_reach_t_end_at_their_own_steps(G, schedule, block):
+    """Uneven transmissive segments advanced to a common t_end: each segment
+    takes its own number of steps and then carries its state over while the
+    others go on (including the interface value at its left end); every
+    segment ends at t_end within the t_end bar of the oracle."""
+    net = network_case(24, seed=13, nmax=120)
+    S = len(net.n_cells)
+    c = oracle_cfg(oracle.EULER, 3, oracle.TRANSMISSIVE)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    t_end = 0.02
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), t_end, 100000)
+    assert np.all(tr == t_end)
+    sim = _gpu_sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                   G.GRPREC_BC_TRANSMISSIVE, schedule=schedule, block=block)
+    try:
+        print(f"network to t_end, schedule {schedule} block {block}", flush=True)
+        steps, _ = sim.run(t_end)
+        qg, vg, _, _ = sim.numpy_state()
+        times = sim.times()
+    finally:
+        sim.close()
+    np.testing.assert_array_equal(times, tr)
+    for s in range(S):
+        c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
