@@ -582,63 +582,52 @@ void euler_step(EulerArgs<M> a) {
       p_learn = wave_learned_pressure(G.g, G.gm1, above0, QL0[0], QL0[1], QL0[2], QR0[0], QR0[1], QR0[2],
                                       a.mlp);
     if (rs_lane) {
-      // Fast pass: the weak-wave solver, in straight-line code, for the
-      // later times too.  The times are independent, and the unrolled loop
-      // gives the scheduler that independent work.  A wave in which some
-      // first-time problem needs the general solver runs the general solver
-      // for all its problems instead (it would wait for those lanes anyway),
-      // unrolled over the times as well.
-      if (__builtin_expect(__ballot(!fast0) == 0ull, 1)) {
-        take(0, o0, QL0, QR0);
-        unsigned slow = 0;
+      // The first time: the weak-wave solver's result, or where it declined
+      // the general solver (a wave in which no lane declined skips that
+      // code).  Above the gate the general solver starts from the learned
+      // proposal, and the later times from the first time's star pressure
+      // shifted by the change of the PVRS estimate; below it (and without
+      // gating) every time starts from PVRS.
+      RSOut og = o0;
+      if (__builtin_expect(__ballot(!fast0) != 0ull, 0)) {
+        if (!fast0) {
+          err |= interact(G, QL0, QR0, p_learn, a.max_newton, a.newton_tol, og, nullptr, a.gate, gated);
+          og.learned = og.strong && p_learn > 0.0;
+        }
+      }
+      take(0, og, QL0, QR0);
+      const double pg = og.strong ? og.pstar : 0.0, pvg = og.strong ? og.pv : 0.0;
+      // The later times: the weak-wave solver in straight-line code (the
+      // times are independent, and the unrolled loop gives the scheduler
+      // that independent work), then the general solver for the problems it
+      // declined.  A lane takes its results in the same order whatever the
+      // other lanes of its wave do, so the results do not depend on the
+      // tiling.
+      unsigned slow = 0;
+#pragma unroll
+      for (int b = 1; b < NT; ++b) {
+        double QL[3], QR[3];
+        load(b, QL, QR);
+        RSOut o;
+        bool fast;
+        if (TR && b == N) {  // end-of-step datum by the two-rarefaction solver
+          err |= trrs_interact(G, QL, QR, o);
+          fast = true;
+        } else {
+          bool above_b;
+          fast = weak_interact(G, QL, QR, a.newton_tol, false, a.gate, o, above_b);
+        }
+        if (fast) take(b, o, QL, QR);
+        else slow |= 1u << b;
+      }
+      if (__builtin_expect(slow != 0, 0)) {
 #pragma unroll
         for (int b = 1; b < NT; ++b) {
+          if (!((slow >> b) & 1u)) continue;
           double QL[3], QR[3];
           load(b, QL, QR);
           RSOut o;
-          bool fast;
-          if (TR && b == N) {  // end-of-step datum by the two-rarefaction solver
-            err |= trrs_interact(G, QL, QR, o);
-            fast = true;
-          } else {
-            bool above_b;
-            fast = weak_interact(G, QL, QR, a.newton_tol, false, a.gate, o, above_b);
-          }
-          if (fast) take(b, o, QL, QR);
-          else slow |= 1u << b;
-        }
-        // the few later-time problems the weak-wave solver declined (first
-        // time below the gate: PVRS start)
-        if (__builtin_expect(slow != 0, 0)) {
-#pragma unroll 1
-          for (int b = 1; b < NT; ++b) {
-            if (!((slow >> b) & 1u)) continue;
-            double QL[3], QR[3];
-            load(b, QL, QR);
-            RSOut o;
-            err |= interact(G, QL, QR, 0.0, a.max_newton, a.newton_tol, o);
-            take(b, o, QL, QR);
-          }
-        }
-      } else {
-        // General solver.  Above the gate the first time starts from the
-        // learned proposal and the later times from the first time's star
-        // pressure, shifted by the change of the PVRS estimate; below it (and
-        // without gating) every time starts from PVRS.
-        RSOut og;
-        err |= interact(G, QL0, QR0, p_learn, a.max_newton, a.newton_tol, og, nullptr, a.gate, gated);
-        og.learned = og.strong && p_learn > 0.0;
-        take(0, og, QL0, QR0);
-        const double pg = og.strong ? og.pstar : 0.0, pvg = og.strong ? og.pv : 0.0;
-#pragma unroll
-        for (int b = 1; b < NT; ++b) {
-          double QL[3], QR[3];
-          load(b, QL, QR);
-          RSOut o;
-          if (TR && b == N)
-            err |= trrs_interact(G, QL, QR, o);
-          else
-            err |= interact(G, QL, QR, pg, a.max_newton, a.newton_tol, o, nullptr, 0.0, false, pvg);
+          err |= interact(G, QL, QR, pg, a.max_newton, a.newton_tol, o, nullptr, 0.0, false, pvg);
           take(b, o, QL, QR);
         }
       }

@@ -340,3 +340,31 @@ def test_network_segments_reach_t_end_at_their_own_steps(G, schedule, block):
         c0, c1 = net.cell_off[s], net.cell_off[s + 1]
         assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= T_END, s
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
+
+
+def test_results_do_not_depend_on_the_tiling(G):
+    """Shock tubes (strong Riemann problems next to weak ones in the same
+    waves) and a smooth network, 20 steps under every tile order and width:
+    the states are bitwise equal, since each lane's solver choices and the
+    order in which it takes its results do not depend on the other lanes."""
+    tubes = I.tube_network(n_seg=300, seed=5)
+    net = network_case(60, seed=3, nmax=400)
+    for name, nw, recon, lam in (("tubes", tubes, 1, 10.0), ("network", net, 0, 1e9)):
+        ref = None
+        for schedule, block in ((1, 64), (2, 64), (2, 128), (3, 256), (1, 256)):
+            sim = _gpu_sim(G, G.GRPREC_EULER, 3, nw.n_cells, nw.lengths, nw.q, nw.vl, nw.vr,
+                           G.GRPREC_BC_TRANSMISSIVE, schedule=schedule, block=block, recon=recon,
+                           nl_lambda_c=lam)
+            try:
+                print(f"{name} tiling {schedule}/{block}", flush=True)
+                steps, _ = sim.run(1e9, 20)
+                assert steps == 20
+                qg, vg, _, _ = sim.numpy_state()
+                t = sim.times()
+            finally:
+                sim.close()
+            if ref is None:
+                ref = (qg, vg, t)
+            else:
+                assert np.array_equal(qg, ref[0]) and np.array_equal(vg, ref[1]), (name, schedule, block)
+                assert np.array_equal(t, ref[2])
