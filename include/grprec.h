@@ -128,8 +128,10 @@ typedef struct {
   const float *mlp_params; /* device, GRPREC_MLP_NPARAMS floats; needed for GUESS_MLP */
   double mlp_gate;     /* relative data jump |dp|/pbar + |drho|/rhobar + |du|/cbar of an
                           interface's first Riemann problem above which the learned and
-                          warm starts are taken; below it Newton starts from PVRS
-                          (default 0.1; negative: always) */
+                          warm starts are taken; below it Newton starts from PVRS, and so
+                          does every problem the weak-wave path takes (both waves weak,
+                          one Newton step from PVRS) (default 0.1; negative: the learned
+                          start for every problem) */
   int warm_start;      /* 1: at interfaces above the gate, the later Riemann problems start
                           from the first time's p*, moved by the change of the PVRS
                           estimate between the two problems (implied by GUESS_MLP) */

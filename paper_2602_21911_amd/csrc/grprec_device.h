@@ -409,6 +409,16 @@ __device__ __forceinline__ bool jump_exceeds(const Prim &L, const Prim &R, doubl
   return gate < 0.0 || lhs > gate * pbar * rbar * cbar;
 }
 
+// jump_exceeds() on conserved data; false for a non-physical state (the
+// general solver reports it).
+__device__ __forceinline__ bool jump_exceeds_q(const Gas &G, const double QL[3], const double QR[3],
+                                               double gate) {
+  Prim L, R;
+  const bool okl = to_prim(G, QL[0], QL[1], QL[2], L);
+  const bool okr = to_prim(G, QR[0], QR[1], QR[2], R);
+  return okl && okr && jump_exceeds(L, R, gate);
+}
+
 // The network's star-pressure proposal, or 0 when it is not positive and
 // finite.  Kept out of line: it is large and, behind the gate, rarely taken.
 // Arguments travel by value: a reference to a local would put that local in
@@ -587,10 +597,9 @@ __device__ __forceinline__ unsigned interact(const Gas &G, const double QL[3], c
 // to second order, the third-order remainder is below 5e-17 rho_K), and the
 // shock speed the expansion of its square root (remainder below 1e-16 c_K).
 // It returns false, leaving o unspecified, whenever the problem needs the
-// general solver: a non-physical or vacuum state, a jump above the gate when
-// test_gate is set (then `above` is set), a start or star pressure outside
-// the weak range, a Newton step that does not meet the tolerance, or a
-// transonic rarefaction.
+// general solver: a non-physical or vacuum state, a start or star pressure
+// outside the weak range, a Newton step that does not meet the tolerance, or
+// a transonic rarefaction.
 struct WeakPrim {
   double r, u, p, ip, c, irc;  // irc = 1/(rho c)
 };
@@ -619,19 +628,12 @@ __device__ __forceinline__ bool weak_prim(const Gas &G, double r, double m, doub
 }
 
 __device__ __forceinline__ bool weak_interact(const Gas &G, const double QL[3], const double QR[3], double tol,
-                                              bool test_gate, double gate, RSOut &o, bool &above) {
+                                              RSOut &o) {
   WeakPrim L, R;
   const bool okl = weak_prim(G, QL[0], QL[1], QL[2], L);
   const bool okr = weak_prim(G, QR[0], QR[1], QR[2], R);
   const double du = R.u - L.u;
   bool ok = okl && okr && (G.two_gm1 * (L.c + R.c) > du);
-  above = false;
-  if (test_gate) {  // the jump test of jump_exceeds(), without divisions
-    const double pbar = 0.5 * (L.p + R.p), rbar = 0.5 * (L.r + R.r), cbar = 0.5 * (L.c + R.c);
-    const double lhs = fabs(R.p - L.p) * rbar * cbar + fabs(R.r - L.r) * pbar * cbar + fabs(du) * pbar * rbar;
-    above = ok && (gate < 0.0 || lhs > gate * pbar * rbar * cbar);
-    ok = ok && !above;
-  }
   // PVRS start, floored as in pvrs()
   const double ppv = 0.5 * (L.p + R.p) - 0.125 * du * (L.r + R.r) * (L.c + R.c);
   const double fl = 1e-6 * fmin(L.p, R.p);

@@ -566,14 +566,18 @@ void euler_step(EulerArgs<M> a) {
         for (int v = 0; v < 3; ++v) VR[v] = o.Q[v];
       }
     };
-    // The first time: the weak-wave solver, which also tests the interface's
-    // jump against the gate when learned or warm starts are on.
+    // The first time: the weak-wave solver.  With learned or warm starts on,
+    // the problems it declines are tested against the gate (a problem it
+    // takes is done in one Newton step from PVRS: no start would do better);
+    // a negative gate takes the learned start for every problem.
     double QL0[3] = {1.0, 0.0, 1.0}, QR0[3] = {1.0, 0.0, 1.0};
     RSOut o0;
     bool fast0 = false, above0 = false;
     if (rs_lane) {
       load(0, QL0, QR0);
-      fast0 = weak_interact(G, QL0, QR0, a.newton_tol, gated, a.gate, o0, above0);
+      const bool always = gated && a.gate < 0.0;
+      fast0 = !always && weak_interact(G, QL0, QR0, a.newton_tol, o0);
+      if (gated && !fast0) above0 = jump_exceeds_q(G, QL0, QR0, a.gate);
     }
     // learned starts of the interfaces above the gate, evaluated by the whole
     // wave (every lane is active here)
@@ -614,8 +618,7 @@ void euler_step(EulerArgs<M> a) {
           err |= trrs_interact(G, QL, QR, o);
           fast = true;
         } else {
-          bool above_b;
-          fast = weak_interact(G, QL, QR, a.newton_tol, false, a.gate, o, above_b);
+          fast = weak_interact(G, QL, QR, a.newton_tol, o);
         }
         if (fast) take(b, o, QL, QR);
         else slow |= 1u << b;
