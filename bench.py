@@ -432,7 +432,7 @@ def trace_run(args, G, torch, I, learn):
     and K timed steps, so a kernel trace's launches of the step kernel are
     exactly these steps."""
     ds = learn.build_dataset(args.train_n)
-    P, _ = learn.train(ds, epochs=args.epochs)
+    P, _ = learn.train(ds, epochs=args.epochs, lr=args.lr, lr_final=1e-5)
     net = I.network(n_seg=args.segments, seed=I.SEED_NETWORK)
     cells = int(net.n_cells.sum())
     sim = make_network(G, net, G.GRPREC_GUESS_MLP, P, args.schedule, args.block)
@@ -454,7 +454,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--segments", type=int, default=10000)
     ap.add_argument("--train-n", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=3e-3, help="Adam step size, falling along a half"
+                    " cosine to 1e-5 over the training run")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -499,14 +501,15 @@ def main():
     if not args.no_mlp:
         t0 = time.perf_counter()
         ds = learn.build_dataset(args.train_n)
-        P, hist = learn.train(ds, epochs=args.epochs)
+        P, hist = learn.train(ds, epochs=args.epochs, lr=args.lr, lr_final=1e-5)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         WL, WR = I.random_tube_states(I.SEED_TUBES_HELDOUT, 100_000)
         ev = learn.evaluate(P, torch.from_numpy(WL).cuda(), torch.from_numpy(WR).cuda())
         params = P
         mlp = {"train_samples": int(ds.x.shape[0]), "vacuum_dropped": ds.n_vacuum,
-               "epochs": args.epochs, "final_loss": hist[-1], "train_s": t_train, "heldout": ev}
+               "epochs": args.epochs, "lr": args.lr, "lr_final": 1e-5, "final_loss": hist[-1],
+               "train_s": t_train, "heldout": ev}
         log(f"mlp trained in {t_train:.1f}s, loss {hist[-1]:.3e}, held-out {ev}")
 
     res = bench_network(args, G, torch, params)

@@ -99,8 +99,10 @@ def init_params(x, seed: int = 0, device: str = "cuda"):
 
 
 def train(ds: Dataset, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
-          device: str = "cuda", log=None):
-    """Adam on the mean-squared error of ln(p*/pbar); returns (params, history)."""
+          device: str = "cuda", log=None, lr_final: float | None = None):
+    """Adam on the mean-squared error of ln(p*/pbar); returns (params, history).
+    With lr_final the step size falls from lr to lr_final along a half cosine
+    over the run."""
     import torch
     n = ds.x.shape[0]
     if n < batch:
@@ -115,6 +117,7 @@ def train(ds: Dataset, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, se
     hist = []
     step = 0
     t0 = time.time()
+    total = epochs * max(1, (n - batch) // batch + 1)
     for ep in range(epochs):
         perm = torch.randperm(n, device=device, generator=gen)
         ep_loss = torch.zeros((), dtype=torch.float64, device=device)
@@ -125,7 +128,10 @@ def train(ds: Dataset, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, se
             yb = ds.y[idx].contiguous()
             G.grprec_mlp_loss_grad(P, xb, yb, grad, loss, work)
             step += 1
-            G.grprec_mlp_adam(P, grad, m, v, step, lr)
+            lr_s = lr
+            if lr_final is not None:
+                lr_s = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * (step - 1) / total))
+            G.grprec_mlp_adam(P, grad, m, v, step, lr_s)
             ep_loss += loss[0].double()
             nb += 1
         hist.append(float(ep_loss.item() / max(1, nb)))
