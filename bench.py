@@ -94,16 +94,16 @@ def timed_run(sim, steps: int, torch):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def make_network(G, net, guess, params, schedule, block=0):
+def make_network(G, net, guess, params, schedule, block=0, gate=0.1):
     return G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
                         bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params,
-                        schedule=schedule, block=block)
+                        schedule=schedule, block=block, mlp_gate=gate)
 
 
-def flops_per_launch(G, net, guess, params, schedule, block):
+def flops_per_launch(G, net, guess, params, schedule, block, gate=0.1):
     """Operation count of one step from the solver's own iteration counters
     (an untimed run with counters on)."""
-    sim = make_network(G, net, guess, params, schedule, block)
+    sim = make_network(G, net, guess, params, schedule, block, gate)
     try:
         G.grprec_enable_stats(sim.h, True)
         k = 3
@@ -122,14 +122,14 @@ def flops_per_launch(G, net, guess, params, schedule, block):
                    "mlp_guesses_per_step": st["mlp_guesses"] / k}
 
 
-def bench_network(args, G, torch, params):
+def bench_network(args, G, torch, params, gate=0.1):
     from paper_2602_21911_amd import inputs as I
     net = I.network(n_seg=args.segments, seed=I.SEED_NETWORK)
     cells = int(net.n_cells.sum())
     out = {"cells": cells}
     # batched + learned guess (headline), autotuned schedule
     sim = make_network(G, net, G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS,
-                       params, G.GRPREC_SCHED_AUTO)
+                       params, G.GRPREC_SCHED_AUTO, 0, gate)
     try:
         sched, block = G.grprec_get_schedule(sim.h)
         sim.run(1e9, args.warmup)
@@ -156,15 +156,15 @@ def bench_network(args, G, torch, params):
     finally:
         sim.close()
     fl, it = flops_per_launch(G, net, G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS,
-                              params, sched, block)
+                              params, sched, block, gate)
     out["flops_per_step"] = fl
     out["iterations"] = it
     out["batched_mlp"]["learned_starts_per_step"] = it["mlp_guesses_per_step"]
     out["batched_mlp"]["learned_start_note"] = (
         "the learned start is taken only at interfaces whose first Riemann problem jumps by more than"
-        " the gate (0.1); on this smooth network that happens %g times per step, so this form runs the"
+        " the gate (%.3g); on this smooth network that happens %g times per step, so this form runs the"
         " PVRS start's arithmetic; the tube network measures what the learned start gains"
-        % it["mlp_guesses_per_step"])
+        % (gate, it["mlp_guesses_per_step"]))
     out["net"] = net
     return out
 
@@ -242,12 +242,12 @@ def bench_small_case(G, torch, I, cfl=0.9):
 
 
 def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, recon, datum=0,
-                  nl_lambda_c=LAMBDA_C_PRINTED):
+                  nl_lambda_c=LAMBDA_C_PRINTED, gate=0.1):
     """Rate of one batched form, and its solver counters over the same steps
     (counted in a second, untimed run)."""
     cells = int(net.n_cells.sum())
     kw = dict(bc=G.GRPREC_BC_TRANSMISSIVE, guess=guess, mlp_params=params, schedule=schedule,
-              block=block, recon=recon, datum=datum, nl_lambda_c=nl_lambda_c)
+              block=block, recon=recon, datum=datum, nl_lambda_c=nl_lambda_c, mlp_gate=gate)
     sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr, **kw)
     try:
         sched, blk = G.grprec_get_schedule(sim.h)
@@ -275,7 +275,7 @@ def _network_form(G, torch, net, guess, params, schedule, block, steps, warmup, 
     return out
 
 
-def bench_tube_network(G, torch, params, steps=100, warmup=10):
+def bench_tube_network(G, torch, params, steps=100, warmup=10, gate=0.1):
     """10^4 shock tubes (GRPrecNL, order 3): the discontinuous workload on
     which the learned Newton start can matter; PVRS vs learned start, same
     schedule.  GRPrecNL runs with lambda_C = 10: the tube family was chosen as
@@ -289,7 +289,8 @@ def bench_tube_network(G, torch, params, steps=100, warmup=10):
            "cells": int(net.n_cells.sum()), "nl_lambda_c": lam}
     first = G.GRPREC_GUESS_MLP if params is not None else G.GRPREC_GUESS_PVRS
     a = _network_form(G, torch, net, first, params, G.GRPREC_SCHED_AUTO, 0, steps, warmup, 1,
-                      nl_lambda_c=lam)
+                      nl_lambda_c=lam, gate=gate)
+    a["mlp_gate"] = gate
     out["batched_mlp" if params is not None else "batched_pvrs"] = a
     if params is not None:
         out["batched_pvrs"] = _network_form(G, torch, net, G.GRPREC_GUESS_PVRS, None, a["schedule"],
@@ -433,9 +434,10 @@ def trace_run(args, G, torch, I, learn):
     exactly these steps."""
     ds = learn.build_dataset(args.train_n)
     P, _ = learn.train(ds, epochs=args.epochs, lr=args.lr, lr_final=1e-5)
+    gate, _ = learn.calibrate_gate(P, *I.random_tube_states(I.SEED_TUBES_GATE, 100_000))
     net = I.network(n_seg=args.segments, seed=I.SEED_NETWORK)
     cells = int(net.n_cells.sum())
-    sim = make_network(G, net, G.GRPREC_GUESS_MLP, P, args.schedule, args.block)
+    sim = make_network(G, net, G.GRPREC_GUESS_MLP, P, args.schedule, args.block, gate)
     try:
         sim.run(1e9, args.warmup)
         sec, _ = timed_run(sim, args.steps, torch)
@@ -498,6 +500,7 @@ def main():
 
     params = None
     mlp = None
+    gate = 0.1
     if not args.no_mlp:
         t0 = time.perf_counter()
         ds = learn.build_dataset(args.train_n)
@@ -506,13 +509,15 @@ def main():
         t_train = time.perf_counter() - t0
         WL, WR = I.random_tube_states(I.SEED_TUBES_HELDOUT, 100_000)
         ev = learn.evaluate(P, torch.from_numpy(WL).cuda(), torch.from_numpy(WR).cuda())
+        # the step's gate: chosen on its own seeded set of random problems
+        gate, cal = learn.calibrate_gate(P, *I.random_tube_states(I.SEED_TUBES_GATE, 100_000))
         params = P
         mlp = {"train_samples": int(ds.x.shape[0]), "vacuum_dropped": ds.n_vacuum,
                "epochs": args.epochs, "lr": args.lr, "lr_final": 1e-5, "final_loss": hist[-1],
-               "train_s": t_train, "heldout": ev}
-        log(f"mlp trained in {t_train:.1f}s, loss {hist[-1]:.3e}, held-out {ev}")
+               "train_s": t_train, "heldout": ev, "gate_calibration": cal}
+        log(f"mlp trained in {t_train:.1f}s, loss {hist[-1]:.3e}, held-out {ev}, gate {cal}")
 
-    res = bench_network(args, G, torch, params)
+    res = bench_network(args, G, torch, params, gate)
     net = res.pop("net")
     cells = res["cells"]
     head = res["batched_mlp"]
@@ -558,7 +563,7 @@ def main():
         line["euler_single_domain"] = [bench_euler_single(G, torch, n, order=o)
                                        for o in (2, 3, 4) for n in (1 << 20, 1 << 22)]
         line["network_variants"] = bench_network_variants(G, torch)
-        line["tube_network"] = bench_tube_network(G, torch, params)
+        line["tube_network"] = bench_tube_network(G, torch, params, gate=gate)
         line["small_case"] = bench_small_case(G, torch, I)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)

@@ -28,6 +28,7 @@ SEED_NETWORK = 20260221
 SEED_TUBES_TRAIN = 20260222
 SEED_TUBES_HELDOUT = 20260223
 SEED_TUBE_NETWORK = 20260224
+SEED_TUBES_GATE = 20260225
 
 
 def grid(n: int, x0: float = 0.0, length: float = 1.0):

@@ -10,6 +10,9 @@ Labels are the exact star pressures from the library's own FP64 Newton solver
 (``grprec_riemann_batch``, 1e-12 relative); vacuum cases are dropped.
 Training runs the library's forward/backward/Adam kernels; torch only holds
 the buffers, draws the seeded shuffles and computes the feature normaliser.
+The step's gate (the data jump above which an interface's first problem
+starts from the network) is then chosen on a separate seeded set of random
+problems as the split that minimises their Newton iterations.
 """
 from __future__ import annotations
 
@@ -165,6 +168,68 @@ def evaluate(P, wl, wr, gamma: float = 1.4, gate: float = -1.0):
         "max_rel_pstar_diff": rel,
         "fallback_rate": float(fallback.double().mean().item()),
     }
+
+
+def jump_size(wl, wr, gamma: float = 1.4):
+    """The relative data jump the step's gate compares:
+    |p_R - p_L| / pbar + |rho_R - rho_L| / rhobar + |u_R - u_L| / cbar with
+    pbar, rhobar, cbar the means of the two sides (host float64 [n,3]
+    primitive states in, [n] out)."""
+    wl = np.asarray(wl, dtype=np.float64)
+    wr = np.asarray(wr, dtype=np.float64)
+    cl = np.sqrt(gamma * wl[:, 2] / wl[:, 0])
+    cr = np.sqrt(gamma * wr[:, 2] / wr[:, 0])
+    pbar = 0.5 * (wl[:, 2] + wr[:, 2])
+    rbar = 0.5 * (wl[:, 0] + wr[:, 0])
+    cbar = 0.5 * (cl + cr)
+    return (np.abs(wr[:, 2] - wl[:, 2]) / pbar + np.abs(wr[:, 0] - wl[:, 0]) / rbar
+            + np.abs(wr[:, 1] - wl[:, 1]) / cbar)
+
+
+def best_split(jump, it_pvrs, it_learned):
+    """Gate minimising the total Newton iterations when problems whose jump
+    exceeds it start from the learned proposal and the others from PVRS.
+    Returns (gate, total at that gate, total all PVRS, total all learned).
+    The gate lies halfway between the largest jump left to PVRS and the
+    smallest one given to the network (0 when every problem goes to the
+    network, the largest jump when none does)."""
+    j = np.asarray(jump, dtype=np.float64)
+    order = np.argsort(j, kind="stable")
+    js = j[order]
+    a = np.asarray(it_pvrs, dtype=np.float64)[order]
+    b = np.asarray(it_learned, dtype=np.float64)[order]
+    # total(k): the k smallest jumps from PVRS, the rest from the network
+    total = (np.concatenate([[0.0], np.cumsum(a)])
+             + np.concatenate([np.cumsum(b[::-1])[::-1], [0.0]]))
+    # a threshold cannot separate equal jumps
+    cut = np.ones(len(js) + 1, dtype=bool)
+    cut[1:-1] = js[1:] > js[:-1]
+    k = int(np.argmin(np.where(cut, total, np.inf)))
+    if k == 0:
+        gate = 0.0
+    elif k == len(js):
+        gate = float(js[-1])
+    else:
+        gate = 0.5 * float(js[k - 1] + js[k])
+    return gate, float(total[k]), float(total[-1]), float(total[0])
+
+
+def calibrate_gate(P, wl, wr, gamma: float = 1.4):
+    """The step's gate for the trained network P: Newton iterations from PVRS
+    and from the learned start on the given problems (host float64 [n,3]
+    primitive states; the library's batched solver), split by best_split.
+    Returns (gate, summary)."""
+    import torch
+    dl = torch.from_numpy(np.ascontiguousarray(wl)).cuda()
+    dr = torch.from_numpy(np.ascontiguousarray(wr)).cuda()
+    _, it0 = G.grprec_riemann_batch(dl, dr, gamma=gamma, guess=G.GRPREC_GUESS_PVRS)
+    _, it1 = G.grprec_riemann_batch(dl, dr, gamma=gamma, guess=G.GRPREC_GUESS_MLP, mlp_params=P, gate=-1.0)
+    a = it0.cpu().numpy()
+    b = it1.cpu().numpy()
+    ok = (a > 0) & (b > 0)
+    gate, tot, tot_pvrs, tot_learned = best_split(jump_size(wl, wr, gamma)[ok], a[ok], b[ok])
+    return gate, {"problems": int(ok.sum()), "gate": gate, "newton_iters": tot,
+                  "newton_iters_all_pvrs": tot_pvrs, "newton_iters_all_learned": tot_learned}
 
 
 def main():

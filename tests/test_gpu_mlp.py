@@ -88,6 +88,18 @@ def test_training_gains_over_pvrs(G):
     assert ev["mlp_mean"] < ev["pvrs_mean"], ev
     assert ev["max_rel_pstar_diff"] <= 1e-11, ev
     assert 0.0 <= ev["fallback_rate"] < 1e-3, ev
+    # the gate chosen on a separate set: the library's solver, gated by the
+    # device's own jump test, spends the Newton iterations the host's split
+    # predicted, no more than either start alone
+    GL, GR = I.random_tube_states(I.SEED_TUBES_GATE, 20_000)
+    gate, cal = learn.calibrate_gate(P, GL, GR)
+    _, it = G.grprec_riemann_batch(torch.from_numpy(GL).cuda(), torch.from_numpy(GR).cuda(),
+                                   guess=G.GRPREC_GUESS_MLP, mlp_params=P, gate=gate)
+    it = it.cpu().numpy()
+    got = float(it[it > 0].sum())
+    assert cal["problems"] == int((it > 0).sum())
+    assert got == cal["newton_iters"], (got, cal)
+    assert got <= min(cal["newton_iters_all_pvrs"], cal["newton_iters_all_learned"]), cal
     # the learned start leaves every star pressure at the oracle's value
     ps, it = G.grprec_riemann_batch(torch.from_numpy(WL[:500]).cuda(), torch.from_numpy(WR[:500]).cuda(),
                                     guess=G.GRPREC_GUESS_MLP, mlp_params=P)
