@@ -1,5 +1,7 @@
-"""Pins of the float64 network reference: the chain-rule gradient against
-central differences, the features against their definition's invariances."""
+"""Pins of the float64 network reference: the forward pass against closed
+forms of single-path parameter blocks, the features against a hand-computed
+case and their definition's invariances, the chain-rule gradients against
+central differences."""
 import numpy as np
 
 from oracle import mlp
