@@ -87,7 +87,16 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
 #ifndef ADV_PASSES
 #define ADV_PASSES 4  // runs per wave per block chunk (4 measured best of 1, 2, 4, 6, 8)
 #endif
-#define ADV_RUN 63    // cells a wave updates per run (64 lanes, one upwind overlap)
+
+// Cells a wave updates per run.  A reconstruction reads the lanes on either
+// side of its own (and the second one to the right for GRPrecNL at degree 4,
+// which reads V_{i+3/2}), and an update reads its upwind neighbour's
+// reconstruction, so of 64 lanes 61 (60) update cells and the rest only
+// hold data; no lane loads anything beyond its own cell.
+template <int M, bool NL>
+constexpr int adv_run() {
+  return (NL && M == 4) ? 60 : 61;
+}
 
 // SRC: with the relaxation source S(q) = -kappa q the predictor is the
 // space-time DG evolution with the implicit source instead of the exact
@@ -171,15 +180,16 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
     }
     return V(j);
   };
-  // A wave advances runs of ADV_RUN = 63 consecutive cells.  Its 64th lane
-  // holds the run's upwind neighbour (lane 0 for lambda > 0, lane 63 for
-  // lambda < 0), so every lane reconstructs one cell and the upwind lane's
-  // flux mean and end-of-step datum reach the next lane by a lane shift.  A block
-  // takes chunks of 4 waves x ADV_PASSES runs.  Blocks are dispatched to the 8
-  // XCDs round-robin, so block b works on chunk (b % 8) * per + b / 8:
-  // consecutive chunks run on one XCD and the cache lines they share at their
-  // ends are read once through its L2.
-  constexpr int RUN = ADV_RUN;
+  // A wave advances runs of RUN consecutive cells.  Lane l holds cell
+  // base + l - OFF: the run's upwind neighbour and the reconstructions' outer
+  // data sit in the lanes around the updated ones, so every lane loads only
+  // its own cell's data, neighbours' values arrive by lane shifts, and the
+  // upwind lane's flux mean and end-of-step datum reach the next lane the same
+  // way.  A block takes chunks of 4 waves x ADV_PASSES runs.  Blocks are
+  // dispatched to the 8 XCDs round-robin, so block b works on chunk
+  // (b % 8) * per + b / 8: consecutive chunks run on one XCD and the cache
+  // lines they share at their ends are read once through its L2.
+  constexpr int RUN = adv_run<M, NL>();
   constexpr int CH = 4 * ADV_PASSES * RUN;
   const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
   const int nch = (n + CH - 1) / CH;
@@ -191,13 +201,16 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   for (int r = 0; r < ADV_PASSES; ++r) {
     const int base = chunk * CH + (r * 4 + wave) * RUN;  // first cell the run updates
     if (base >= n) break;                                 // uniform over the wave
-    const int i = pos ? base + lane - 1 : base + lane;    // this lane's cell
-    const bool own = pos ? lane >= 1 : lane < RUN;        // updated by this run
+    // updated lanes OFF .. OFF + RUN - 1: for lambda > 0 the upwind lane and
+    // the left neighbour it reads lie below them, for lambda < 0 one lane
+    // below and the upwind lane with its right data above
+    const int OFF = pos ? 2 : 1;
+    const int i = base + lane - OFF;                      // this lane's cell
+    const bool own = lane >= OFF && lane < OFF + RUN;     // updated by this run
     // Every lane within two cells of the domain holds the average of its cell
     // and the value at the cell's left interface (wrapped when periodic; the
     // ghost state beyond a transmissive end); a reconstruction takes its
-    // neighbours' values from the adjacent lanes, and only the wave's edge
-    // lanes load theirs.
+    // neighbours' values from the adjacent lanes.
     // (cells -2 .. n+1 and interfaces -2 .. n+2 are what reconstructions of
     // cells -1 .. n read; a single +-n wrap keeps them in range for n >= 2)
     double qk = 0.0, vk = 0.0;
@@ -221,18 +234,9 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       mean_s = K0 * qk;
       pt_s = P0 * qk;
     }
+    // (lanes at the wave's edges reconstruct from shifted-in copies of their
+    // own data; no updated lane reads their results)
     if (recon && !done) {
-      if (lane == 0) {
-        qm = Q(i - 1);
-        if constexpr (NL && M == 4) vm = VG(i - 1);
-      }
-      if (lane == 63) {
-        qp = Q(i + 1);
-        vp = VG(i + 1);
-      }
-      if constexpr (NL && M == 4) {
-        if (lane >= 62) vpp = VG(i + 2);
-      }
       // interfaces 0 and n of a periodic domain are one interface: cell n-1
       // reads its right value at n, cell 0 its left value at 0
       double vl = vk;
@@ -471,7 +475,7 @@ __global__ void digest(const double *x, long long n, Ctl *ctl) {
 template <int M>
 hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
   (void)grid;
-  const long long ch = 4LL * ADV_PASSES * ADV_RUN;
+  const long long ch = 4LL * ADV_PASSES * (nl ? adv_run<M, true>() : adv_run<M, false>());
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
   if (a.src) {

@@ -67,6 +67,30 @@ def test_advection_nl_parity(G, order, kind, n, bc, lam_c):
         sim.close()
 
 
+@pytest.mark.parametrize("n", [2, 3, 59, 60, 61, 119, 120, 121, 959, 960, 961])
+@pytest.mark.parametrize("lam,bc", [(1.0, 0), (-0.7, 1), (-0.6, 0), (0.6, 1)])
+def test_advection_nl_sizes(G, n, lam, bc):
+    """GRPrecNL advection at the kernel's run and chunk boundaries (60 updated
+    cells per wave and 960 per block chunk at degree 4, 61 and 976 below),
+    tiny domains and both signs of the speed: order 5 reads V_{i+-3/2}."""
+    order = 5 if n % 2 else 3
+    dx, q, vl, vr = I.adv_sin2pi(n)
+    obc = oracle.PERIODIC if bc == 0 else oracle.TRANSMISSIVE
+    gbc = G.GRPREC_BC_PERIODIC if bc == 0 else G.GRPREC_BC_TRANSMISSIVE
+    c = _ocfg(oracle.ADVECTION, order, obc, 10.0, lam=lam)
+    v = oracle.init_interfaces(c, vl, vr)
+    sim = _sim(G, G.GRPREC_ADVECTION, order, [n], [1.0], q, vl, vr, gbc, 10.0, lam=lam)
+    try:
+        print(f"advection NL n={n} order {order} lambda {lam} bc {bc}", flush=True)
+        sim.run(0.05)
+        qr, vr_, tr, kr, _ = oracle.run(c, dx, q, v, 0.0, 0.05)
+        qg, vg, t, steps = sim.numpy_state()
+        assert steps == kr and t == tr
+        assert rel_linf(qg, qr) <= T_END and rel_linf(vg, vr_) <= T_END
+    finally:
+        sim.close()
+
+
 @pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("block", [64, 256])
 def test_euler_nl_density_wave_parity(G, order, block):
