@@ -84,9 +84,13 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
   }
 }
 
-#ifndef ADV_PASSES
-#define ADV_PASSES 4  // runs per wave per block chunk (4 measured best of 1, 2, 4, 6, 8)
-#endif
+// Runs per wave per block chunk.  Measured at 2^25 cells over 1, 2, 3, 4, 8,
+// 12 and 16: the memory-bound GRPrec kernels run best with 2 (more blocks in
+// flight), the arithmetic-bound GRPrecNL kernels with 8.
+template <bool NL>
+constexpr int adv_passes() {
+  return NL ? 8 : 2;
+}
 
 // Cells a wave updates per run.  A reconstruction reads the lanes on either
 // side of its own (and the second one to the right for GRPrecNL at degree 4,
@@ -185,12 +189,13 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   // data sit in the lanes around the updated ones, so every lane loads only
   // its own cell's data, neighbours' values arrive by lane shifts, and the
   // upwind lane's flux mean and end-of-step datum reach the next lane the same
-  // way.  A block takes chunks of 4 waves x ADV_PASSES runs.  Blocks are
+  // way.  A block takes chunks of 4 waves x PASSES runs.  Blocks are
   // dispatched to the 8 XCDs round-robin, so block b works on chunk
   // (b % 8) * per + b / 8: consecutive chunks run on one XCD and the cache
   // lines they share at their ends are read once through its L2.
   constexpr int RUN = adv_run<M, NL>();
-  constexpr int CH = 4 * ADV_PASSES * RUN;
+  constexpr int PASSES = adv_passes<NL>();
+  constexpr int CH = 4 * PASSES * RUN;
   const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
   const int nch = (n + CH - 1) / CH;
   const int per = (nch + 7) / 8;
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   const int chunk = (blk % 8) * per + blk / 8;
   if (chunk >= nch) continue;
 #pragma unroll
-  for (int r = 0; r < ADV_PASSES; ++r) {
+  for (int r = 0; r < PASSES; ++r) {
     const int base = chunk * CH + (r * 4 + wave) * RUN;  // first cell the run updates
     if (base >= n) break;                                 // uniform over the wave
     // updated lanes OFF .. OFF + RUN - 1: for lambda > 0 the upwind lane and
@@ -475,7 +480,8 @@ __global__ void digest(const double *x, long long n, Ctl *ctl) {
 template <int M>
 hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
   (void)grid;
-  const long long ch = 4LL * ADV_PASSES * (nl ? adv_run<M, true>() : adv_run<M, false>());
+  const long long ch = nl ? 4LL * adv_passes<true>() * adv_run<M, true>()
+                          : 4LL * adv_passes<false>() * adv_run<M, false>();
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
   if (a.src) {

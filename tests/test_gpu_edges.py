@@ -28,12 +28,12 @@ def G():
     return grprec
 
 
-@pytest.mark.parametrize("n", [2, 3, 60, 61, 62, 63, 64, 121, 122, 123, 125, 126, 127, 503, 504, 505,
-                               975, 976, 977, 1009])
+@pytest.mark.parametrize("n", [2, 3, 60, 61, 62, 63, 64, 121, 122, 123, 125, 126, 127, 487, 488, 489,
+                               503, 504, 505, 975, 976, 977, 1009])
 @pytest.mark.parametrize("lam,bc", [(1.0, 0), (-0.7, 1), (0.6, 1)])
 def test_advection_sizes(G, n, lam, bc):
     """Run and chunk boundaries of the advection kernel (61 updated cells per
-    wave, 976 per block chunk) and tiny domains, both signs of the speed."""
+    wave, 488 per block chunk) and tiny domains, both signs of the speed."""
     order = 3 if n % 2 else 5
     dx, q, vl, vr = I.adv_sin2pi(n)
     obc = oracle.PERIODIC if bc == 0 else oracle.TRANSMISSIVE

@@ -67,11 +67,11 @@ def test_advection_nl_parity(G, order, kind, n, bc, lam_c):
         sim.close()
 
 
-@pytest.mark.parametrize("n", [2, 3, 59, 60, 61, 119, 120, 121, 959, 960, 961])
+@pytest.mark.parametrize("n", [2, 3, 59, 60, 61, 119, 120, 121, 1919, 1920, 1921, 1952])
 @pytest.mark.parametrize("lam,bc", [(1.0, 0), (-0.7, 1), (-0.6, 0), (0.6, 1)])
 def test_advection_nl_sizes(G, n, lam, bc):
     """GRPrecNL advection at the kernel's run and chunk boundaries (60 updated
-    cells per wave and 960 per block chunk at degree 4, 61 and 976 below),
+    cells per wave and 1920 per block chunk at degree 4, 61 and 1952 below),
     tiny domains and both signs of the speed: order 5 reads V_{i+-3/2}."""
     order = 5 if n % 2 else 3
     dx, q, vl, vr = I.adv_sin2pi(n)
