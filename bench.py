@@ -204,6 +204,58 @@ def advection_lines(G, torch):
     return out
 
 
+def _golden(name):
+    """Rows of a committed table of the paper's printed values."""
+    return np.loadtxt(os.path.join(ROOT, "tests", "golden", name), comments="#", ndmin=2)
+
+
+def bench_paper_tables(G, torch, I):
+    """The runs of the paper's two FV+GRPrec convergence tables (Sec. 4.2.3:
+    advection of sin^4(pi x) on periodic [-1,1], N = 16..256; Sec. 4.3.1:
+    Euler density wave rho = 1 + 0.2 sin 2 pi x, u = 1, p = 2 on periodic
+    [0,1], N = 40..640; orders 2-5, C_CFL 0.9, t_out 4) run whole on the GPU
+    (graph-captured), with their errors against the exact cell averages, next
+    to the errors and CPU seconds the paper prints (its hardware is not
+    stated; its Euler magnitudes do not fit the stated unit domain, so only
+    their rates are comparable)."""
+    err = {0: {}, 1: {}}
+    for sysid, name in ((0, "paper_advection_grprec.txt"), (1, "paper_euler_grprec.txt")):
+        for r in _golden(name):
+            err[sysid][(int(r[0]), int(r[1]))] = (float(r[2]), float(r[3]))
+    out = {"advection": [], "euler": [],
+           "note": "gpu_s: whole run on the GPU (grprec_run, HIP events); paper_cpu_s: the paper's"
+                   " printed CPU seconds for the same run, hardware not stated"}
+    for sysid, order, n, cpu_s in _golden("paper_cpu_seconds.txt"):
+        sysid, order, n = int(sysid), int(order), int(n)
+        if sysid == 0:
+            dx, q, vl, vr = I.adv_sin4(n)
+            sim = G.Simulation(G.GRPREC_ADVECTION, order, [n], [2.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
+        else:
+            dx, q, vl, vr = I.euler_density_wave(n, amp=0.2, u=1.0, p=2.0)
+            sim = G.Simulation(G.GRPREC_EULER, order, [n], [1.0], q, vl, vr, bc=G.GRPREC_BC_PERIODIC)
+        try:
+            stream = torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            steps, _ = sim.run(4.0)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gpu_s = e0.elapsed_time(e1) / 1e3
+            qg, _, t, _ = sim.numpy_state()
+        finally:
+            sim.close()
+        exact = I.adv_sin4_exact_avg(n, 4.0) if sysid == 0 else I.euler_density_wave_exact_rho(n, 4.0)
+        e = np.abs(qg[0] - exact)
+        pl, p1 = err[sysid][(order, n)]
+        out["advection" if sysid == 0 else "euler"].append(
+            {"order": order, "cells": n, "steps": int(steps), "t": t, "linf": float(e.max()),
+             "l1": float(dx * e.sum()), "gpu_s": gpu_s, "paper_linf": pl, "paper_l1": p1,
+             "paper_cpu_s": float(cpu_s)})
+    return out
+
+
 def bench_small_case(G, torch, I, cfl=0.9):
     """Advection of sin 2 pi x on 100 periodic cells, order 3, to t = 1 (112
     steps): a latency-bound case, timed as whole runs through grprec_run
@@ -463,8 +515,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip advection / single-domain lines")
-    ap.add_argument("--only", choices=["all", "advection", "counters", "trace"], default="all",
-                    help="advection: only the advection lines; counters: a short fixed run for"
+    ap.add_argument("--only", choices=["all", "advection", "counters", "trace", "paper"], default="all",
+                    help="advection: only the advection lines; paper: only the runs of the paper's"
+                         " convergence tables; counters: a short fixed run for"
                          " hardware-counter passes (network, advection 2^25, a 256 MB copy);"
                          " trace: the headline network form on a fixed schedule (--schedule,"
                          " --block; no autotuning), W + K steps, for a kernel trace whose every"
@@ -490,6 +543,9 @@ def main():
     if args.only == "advection":
         out = advection_lines(G, torch)
         print(json.dumps({"advection": out}), flush=True)
+        return
+    if args.only == "paper":
+        print(json.dumps({"paper_tables": bench_paper_tables(G, torch, I)}), flush=True)
         return
     if args.only == "counters":
         counters_run(G, torch, I)
@@ -565,6 +621,7 @@ def main():
         line["network_variants"] = bench_network_variants(G, torch)
         line["tube_network"] = bench_tube_network(G, torch, params, gate=gate)
         line["small_case"] = bench_small_case(G, torch, I)
+        line["paper_tables"] = bench_paper_tables(G, torch, I)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)
         line["cpu_all_cores"] = cpu_all_cores(net, args.cpu_steps)

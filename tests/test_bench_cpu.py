@@ -51,3 +51,18 @@ def test_segment_groups_reproduce_the_serial_oracle():
         assert np.array_equal(qs, qf[:, c0:c1])
         assert np.array_equal(vs, vf[:, c0 + a:c1 + b])
         assert np.array_equal(ts, tf[a:b])
+
+
+def test_paper_cpu_table_matches_the_error_tables():
+    """The CPU-seconds table covers exactly the runs of the two printed error
+    tables (orders 2-5; advection N = 16..256, Euler N = 40..640), and the
+    bench reads all three."""
+    import bench
+    cpu = bench._golden("paper_cpu_seconds.txt")
+    assert cpu.shape == (40, 4) and np.all(cpu[:, 3] > 0)
+    for sysid, name, cells in ((0, "paper_advection_grprec.txt", (16, 32, 64, 128, 256)),
+                               (1, "paper_euler_grprec.txt", (40, 80, 160, 320, 640))):
+        err = bench._golden(name)
+        keys = {(int(r[0]), int(r[1])) for r in err}
+        assert keys == {(o, n) for o in (2, 3, 4, 5) for n in cells}
+        assert {(int(r[1]), int(r[2])) for r in cpu if int(r[0]) == sysid} == keys
