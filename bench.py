@@ -512,7 +512,8 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3, help="Adam step size, falling along a half"
                     " cosine to 1e-5 over the training run")
     ap.add_argument("--no-mlp", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="network steps the oracle runs for cpu_baseline (about 11 s on one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip advection / single-domain lines")
     ap.add_argument("--only", choices=["all", "advection", "counters", "trace", "paper"], default="all",
