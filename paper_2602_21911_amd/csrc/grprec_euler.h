@@ -33,9 +33,13 @@ namespace grp {
 // De, Do, Dm, Dc): 7 operations instead of 9 at N = 3, 20 instead of 25 at
 // N = 5.  With the row sums of D zero, the even part's coefficients of one row
 // sum to zero, which removes one term for even N (all of it at N = 2).
-template <int N, class Tab>
-__device__ __forceinline__ void deriv_sym(const Tab &T, const double (&f)[N], double (&g)[N]) {
+// With SCALE the result is c D f: the constants are multiplied by c (the
+// products do not depend on f, so the compiler forms them once per cell).
+template <int N, bool SCALE = false, class Tab>
+__device__ __forceinline__ void deriv_sym(const Tab &T, const double (&f)[N], double (&g)[N],
+                                          double c = 1.0) {
   constexpr int H = N / 2;
+  auto k_ = [&](double v) { return SCALE ? c * v : v; };
   double s[H], d[H];
 #pragma unroll
   for (int k = 0; k < H; ++k) {
@@ -44,19 +48,19 @@ __device__ __forceinline__ void deriv_sym(const Tab &T, const double (&f)[N], do
   }
 #pragma unroll
   for (int x = 0; x < H; ++x) {
-    double o = T.Do[x][0] * d[0];
+    double o = k_(T.Do[x][0]) * d[0];
 #pragma unroll
-    for (int k = 1; k < H; ++k) o = fma(T.Do[x][k], d[k], o);
+    for (int k = 1; k < H; ++k) o = fma(k_(T.Do[x][k]), d[k], o);
     if constexpr (N % 2 == 1) {
-      double e = T.Dm[x] * f[H];
+      double e = k_(T.Dm[x]) * f[H];
 #pragma unroll
-      for (int k = 0; k < H; ++k) e = fma(T.De[x][k], s[k], e);
+      for (int k = 0; k < H; ++k) e = fma(k_(T.De[x][k]), s[k], e);
       g[x] = o + e;
       g[N - 1 - x] = o - e;
     } else if constexpr (H > 1) {
-      double e = T.De[x][0] * (s[0] - s[H - 1]);
+      double e = k_(T.De[x][0]) * (s[0] - s[H - 1]);
 #pragma unroll
-      for (int k = 1; k < H - 1; ++k) e = fma(T.De[x][k], s[k] - s[H - 1], e);
+      for (int k = 1; k < H - 1; ++k) e = fma(k_(T.De[x][k]), s[k] - s[H - 1], e);
       g[x] = o + e;
       g[N - 1 - x] = o - e;
     } else {
@@ -65,10 +69,10 @@ __device__ __forceinline__ void deriv_sym(const Tab &T, const double (&f)[N], do
     }
   }
   if constexpr (N % 2 == 1) {
-    double c = T.Dc[0] * d[0];
+    double m = k_(T.Dc[0]) * d[0];
 #pragma unroll
-    for (int k = 1; k < H; ++k) c = fma(T.Dc[k], d[k], c);
-    g[H] = c;
+    for (int k = 1; k < H; ++k) m = fma(k_(T.Dc[k]), d[k], m);
+    g[H] = m;
   }
 }
 
@@ -346,6 +350,10 @@ void euler_step(EulerArgs<M> a) {
       // tested: it can only meet the tolerance when the flux gradient
       // vanishes, and then the second sweep reproduces it (and stops).
       double qh[3][N][N];
+      // At N = 3 without the source, nu is folded into the derivative's
+      // constants, so D F arrives scaled and each Picard update is three fused
+      // multiply-adds (the source kernels keep the unscaled form).
+      constexpr bool FOLD = (N == 3) && !SRC;
       {
         double F1[3][N];
 #pragma unroll
@@ -353,10 +361,19 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
           double Gd[N];
-          deriv_sym<N>(T, F1[v], Gd);
+          if constexpr (FOLD) {
+            deriv_sym<N, true>(T, F1[v], Gd, nu);
+          } else {
+            deriv_sym<N>(T, F1[v], Gd);
+          }
 #pragma unroll
           for (int x = 0; x < N; ++x) {
-            const double t = nu * Gd[x];
+            double t;
+            if constexpr (FOLD) {
+              t = Gd[x];
+            } else {
+              t = nu * Gd[x];
+            }
 #pragma unroll
             for (int b = 0; b < N; ++b) {
               if constexpr (SRC) {
@@ -390,7 +407,11 @@ void euler_step(EulerArgs<M> a) {
             double f[N], g[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) f[k] = F[v][k][l];
-            deriv_sym<N>(T, f, g);
+            if constexpr (FOLD) {
+              deriv_sym<N, true>(T, f, g, nu);
+            } else {
+              deriv_sym<N>(T, f, g);
+            }
 #pragma unroll
             for (int x = 0; x < N; ++x) Gd[x][l] = g[x];
           }
@@ -404,11 +425,19 @@ void euler_step(EulerArgs<M> a) {
 #pragma unroll
                 for (int l = 0; l < N; ++l) acc += SA[b][l] * Gd[x][l];
                 wb *= gf[b];
+              } else if constexpr (FOLD) {
+#pragma unroll
+                for (int l = 0; l < N; ++l) wb = fma(-T.KW[b][l], Gd[x][l], wb);
               } else {
 #pragma unroll
                 for (int l = 0; l < N; ++l) acc += T.KW[b][l] * Gd[x][l];
               }
-              const double nv = wb - nu * acc;
+              double nv;
+              if constexpr (FOLD) {
+                nv = wb;
+              } else {
+                nv = wb - nu * acc;
+              }
               // non-finite values do not stop the sweep here: they reach the
               // traces and are caught by the physical-state checks
               if constexpr (TEST) {
