@@ -350,10 +350,11 @@ void euler_step(EulerArgs<M> a) {
       // tested: it can only meet the tolerance when the flux gradient
       // vanishes, and then the second sweep reproduces it (and stops).
       double qh[3][N][N];
-      // At N = 3 without the source, nu is folded into the derivative's
-      // constants, so D F arrives scaled and each Picard update is three fused
-      // multiply-adds (the source kernels keep the unscaled form).
-      constexpr bool FOLD = (N == 3) && !SRC;
+      // Up to N = 4 without the source, nu is folded into the derivative's
+      // constants, so D F arrives scaled and each Picard update is N fused
+      // multiply-adds (at N = 5 the twelve scaled constants would spill; the
+      // source kernels keep the unscaled form).
+      constexpr bool FOLD = (N <= 4) && !SRC;
       {
         double F1[3][N];
 #pragma unroll
