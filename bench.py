@@ -256,6 +256,38 @@ def bench_paper_tables(G, torch, I):
     return out
 
 
+def bench_bulk_riemann(G, torch, I, P, gate, n=1_000_000, reps=10):
+    """The bulk Riemann solver (one problem per lane) on n held-out random
+    tube problems: PVRS start, learned start for every problem, learned start
+    above the gate; time per call (HIP events, mean of reps) and the mean
+    Newton iterations."""
+    WL, WR = I.random_tube_states(I.SEED_TUBES_HELDOUT, n)
+    wl = torch.from_numpy(WL).cuda()
+    wr = torch.from_numpy(WR).cuda()
+    ps = torch.empty(n, dtype=torch.float64, device="cuda")
+    it = torch.empty(n, dtype=torch.int32, device="cuda")
+    out = {"problems": n}
+    for name, guess, g in (("pvrs", G.GRPREC_GUESS_PVRS, -1.0), ("learned_all", G.GRPREC_GUESS_MLP, -1.0),
+                           ("learned_above_gate", G.GRPREC_GUESS_MLP, gate)):
+        params = P if guess == G.GRPREC_GUESS_MLP else None
+        for _ in range(2):
+            G.grprec_riemann_batch(wl, wr, guess=guess, mlp_params=params, gate=g, pstar=ps, iters=it)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            G.grprec_riemann_batch(wl, wr, guess=guess, mlp_params=params, gate=g, pstar=ps, iters=it)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        k = it.cpu().numpy()
+        out[name] = {"ms_per_call": ms, "problems_per_s": n / (ms / 1e3),
+                     "newton_mean": float(k[k > 0].mean())}
+    return out
+
+
 def bench_small_case(G, torch, I, cfl=0.9):
     """Advection of sin 2 pi x on 100 periodic cells, order 3, to t = 1 (112
     steps): a latency-bound case, timed as whole runs through grprec_run
@@ -623,6 +655,8 @@ def main():
         line["tube_network"] = bench_tube_network(G, torch, params, gate=gate)
         line["small_case"] = bench_small_case(G, torch, I)
         line["paper_tables"] = bench_paper_tables(G, torch, I)
+        if params is not None:
+            line["mlp"]["bulk_riemann"] = bench_bulk_riemann(G, torch, I, params, gate)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args.cpu_steps)
         line["cpu_all_cores"] = cpu_all_cores(net, args.cpu_steps)
