@@ -16,7 +16,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "grprec_oracle.c")
-_LIB = os.path.join(_HERE, "libgrprec_oracle.so")
+# GRPREC_ORACLE_LIB names another build of the same source to load instead
+# (the tests that plant mistakes in the oracle use it to run the pins against
+# a mutated build); it is never rebuilt from here.
+_LIB_ENV = os.environ.get("GRPREC_ORACLE_LIB")
+_LIB = _LIB_ENV or os.path.join(_HERE, "libgrprec_oracle.so")
+CFLAGS = ["-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+          "-shared"]
 
 OK, E_INVALID, E_NONPHYSICAL, E_VACUUM, E_NEWTON, E_PREDICTOR = 0, -1, -4, -5, -6, -7
 ADVECTION, EULER = 0, 1
@@ -33,9 +39,10 @@ LAMBDA_C_TABLE = 10.0
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
+    if _LIB_ENV:
+        return _LIB
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
-               "-fno-fast-math", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", *CFLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB

@@ -1,0 +1,133 @@
+"""Mistakes planted in the oracle, on the CPU: each entry below rewrites one
+expression of ``oracle/grprec_oracle.c`` the way a plausible slip would (a
+flipped sign, a wrong exponent, a transposed index, swapped operands), builds
+that copy with the oracle's own flags, and runs the oracle's pin tests
+against it.  Every planted mistake must make at least one pin fail; a
+mistake that no pin catches would be a hole in what the pins prove.
+
+The pins run in child processes (``GRPREC_ORACLE_LIB`` points the oracle
+module at the mutated build), several at a time; the pristine oracle is not
+touched.  Mistakes that cannot change any result (the Newton start, which
+the solution does not depend on) are not planted."""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "grprec_oracle.c")
+PINS = ["tests/test_oracle_pieces.py", "tests/test_oracle_riemann.py", "tests/test_oracle_scheme.py",
+        "tests/test_oracle_nl.py", "tests/test_oracle_source.py"]
+
+# (name, expression as written, the planted mistake)
+MUTANTS = [
+    ("rarefaction branch exponent (g-1)/g instead of (g-1)/(2g)",
+     "*f = 2.0 * ck / (g - 1.0) * (pow(pr, (g - 1.0) / (2.0 * g)) - 1.0);",
+     "*f = 2.0 * ck / (g - 1.0) * (pow(pr, (g - 1.0) / g) - 1.0);"),
+    ("shock branch B_K with (g+1)/(g-1)",
+     "double bk = (g - 1.0) / (g + 1.0) * pk;",
+     "double bk = (g + 1.0) / (g - 1.0) * pk;"),
+    ("star velocity with f_L - f_R",
+     "double u = 0.5 * (ul + ur) + 0.5 * (fr - fl);",
+     "double u = 0.5 * (ul + ur) + 0.5 * (fl - fr);"),
+    ("sampling side chosen by u* < 0",
+     "  if (u >= 0.0) {\n    if (p <= pl) { /* left rarefaction */",
+     "  if (u < 0.0) {\n    if (p <= pl) { /* left rarefaction */"),
+    ("left shock star density ratio inverted",
+     "W0[0] = rl * (pml + gm1 / gp1) / (pml * gm1 / gp1 + 1.0); W0[1] = u; W0[2] = p;",
+     "W0[0] = rl * (pml * gm1 / gp1 + 1.0) / (pml + gm1 / gp1); W0[1] = u; W0[2] = p;"),
+    ("Euler energy flux u E",
+     "F[2] = u * (E + p);\n}",
+     "F[2] = u * E;\n}"),
+    ("pressure from E - m u",
+     "double p = (cf->gamma - 1.0) * (E - 0.5 * mom * u);",
+     "double p = (cf->gamma - 1.0) * (E - mom * u);"),
+    ("time matrix with + integral",
+     "K[b * n + l] = orc_lagr(n, s->g, b, 1.0) * orc_lagr(n, s->g, l, 1.0) - integral;",
+     "K[b * n + l] = orc_lagr(n, s->g, b, 1.0) * orc_lagr(n, s->g, l, 1.0) + integral;"),
+    ("space derivative matrix transposed",
+     "acc += s->D[a][k] * F[(v * n + k) * n + l];",
+     "acc += s->D[k][a] * F[(v * n + k) * n + l];"),
+    ("implicit source with - z w",
+     "if (b == l) K[b * n + l] += z * s->w[b];",
+     "if (b == l) K[b * n + l] -= z * s->w[b];"),
+    ("predictor start without K^-1 l(0)",
+     "double val = s->Kinv_l0[b] * w[v * n + a] - nu * acc;",
+     "double val = w[v * n + a] - nu * acc;"),
+    ("end-of-step trace evaluated at t = 0",
+     "for (int b = 0; b < n; ++b) qa1 += s->l1[b] * q[(v * n + a) * n + b];",
+     "for (int b = 0; b < n; ++b) qa1 += s->l0[b] * q[(v * n + a) * n + b];"),
+    ("left neighbour's mean over the right cell",
+     "case 0: a = -1.5; b = -0.5; break;",
+     "case 0: a = 0.5; b = 1.5; break;"),
+    ("interface points -1/2 and +1/2 swapped",
+     "static const double point[7] = {0.0, 0.0, 0.0, -0.5, 0.5, -1.5, 1.5};",
+     "static const double point[7] = {0.0, 0.0, 0.0, 0.5, -0.5, -1.5, 1.5};"),
+    ("Gauss-Legendre weights not halved on [0,1]",
+     "w01[n - 1 - i] = 0.5 * w;",
+     "w01[n - 1 - i] = w;"),
+    ("S_max from u + c",
+     "double si = fabs(W[1]) + c;",
+     "double si = W[1] + c;"),
+    ("update with + nu (F_R - F_L)",
+     "q[vv * n + i] - nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]) + dt * Si[vv * n + i];",
+     "q[vv * n + i] + nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]) + dt * Si[vv * n + i];"),
+    ("source integral with - dt S",
+     "q[vv * n + i] - nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]) + dt * Si[vv * n + i];",
+     "q[vv * n + i] - nu * (Fb[vv * (n + 1) + i + 1] - Fb[vv * (n + 1) + i]) - dt * Si[vv * n + i];"),
+    ("oscillation indicator with dx^(2l-1)",
+     "oi += dx * w[k] * d * d * pow(dx, 2 * l);",
+     "oi += dx * w[k] * d * d * pow(dx, 2 * l - 1);"),
+    ("GRPrecNL central weight with exponent r/2",
+     "double wc = cf->nl_lambda_c / pow(cf->nl_eps + orc_oi_q(m, cc, dx, t->g5, t->w5), cf->nl_r);",
+     "double wc = cf->nl_lambda_c / pow(cf->nl_eps + orc_oi_q(m, cc, dx, t->g5, t->w5), 0.5 * cf->nl_r);"),
+    ("GRPrecNL left and right candidates swapped",
+     "      cl[r] += ML[r * 7 + k] * d[k];\n      cr[r] += MR[r * 7 + k] * d[k];",
+     "      cl[r] += MR[r * 7 + k] * d[k];\n      cr[r] += ML[r * 7 + k] * d[k];"),
+    ("two-rarefaction exponent (g-1)/g",
+     "double gm1 = g - 1.0, gp1 = g + 1.0, z = gm1 / (2.0 * g);",
+     "double gm1 = g - 1.0, gp1 = g + 1.0, z = gm1 / g;"),
+]
+
+
+def _caught(args):
+    k, (name, old, new), work = args
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutant {k} ({name}): expression not found once in the oracle"
+    path = os.path.join(work, f"m{k}.c")
+    lib = os.path.join(work, f"libm{k}.so")
+    with open(path, "w") as fh:
+        fh.write(src.replace(old, new))
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", lib, path, "-lm"])
+    env = dict(os.environ, GRPREC_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu"], cwd=ROOT, env=env, capture_output=True, text=True)
+    # exit 1: some pin failed (caught); 0: every pin passed (survived)
+    return k, name, r.returncode, r.stdout[-400:]
+
+
+def test_every_planted_mistake_fails_a_pin():
+    jobs = max(1, min(8, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 4))
+    with tempfile.TemporaryDirectory() as work:
+        with cf.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(_caught, [(k, m, work) for k, m in enumerate(MUTANTS)]))
+    survived = [(k, name, rc, tail) for k, name, rc, tail in results if rc != 1]
+    assert not survived, "\n".join(f"mutant {k} ({name}): pytest exit {rc}\n{tail}" for k, name, rc, tail in survived)
+
+
+def test_unplanted_oracle_passes_its_pins_in_the_same_harness():
+    """The harness itself: the pristine source, built the same way and run
+    the same way, passes (so a failure above is the planted mistake's)."""
+    with tempfile.TemporaryDirectory() as work:
+        lib = os.path.join(work, "libclean.so")
+        subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", lib, SRC, "-lm"])
+        env = dict(os.environ, GRPREC_ORACLE_LIB=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pieces.py",
+                            "tests/test_oracle_riemann.py", "-x", "-q", "-p", "no:cacheprovider"],
+                           cwd=ROOT, env=env, capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout[-800:]
