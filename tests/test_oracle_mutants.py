@@ -131,3 +131,69 @@ def test_unplanted_oracle_passes_its_pins_in_the_same_harness():
                             "tests/test_oracle_riemann.py", "-x", "-q", "-p", "no:cacheprovider"],
                            cwd=ROOT, env=env, capture_output=True, text=True)
         assert r.returncode == 0, r.stdout[-800:]
+
+
+# The float64 network reference (oracle/mlp.py): the same idea in-process.
+# Each entry rewrites one line of a copy of the module; every test of
+# tests/test_oracle_mlp.py is then run against the copy, and at least one
+# must fail.
+MLP_MUTANTS = [
+    ("first weight block read transposed",
+     "W1 = P[0:192].reshape(32, 6)", "W1 = P[0:192].reshape(6, 32).T"),
+    ("forward standardises by multiplying with std",
+     "def forward(P, x):\n    W1, b1, W2, b2, W3, b3, mean, std = unpack(P)\n"
+     "    z = (np.asarray(x, dtype=np.float64) - mean) / std",
+     "def forward(P, x):\n    W1, b1, W2, b2, W3, b3, mean, std = unpack(P)\n"
+     "    z = (np.asarray(x, dtype=np.float64) - mean) * std"),
+    ("forward adds the first bias after tanh",
+     "def forward(P, x):\n    W1, b1, W2, b2, W3, b3, mean, std = unpack(P)\n"
+     "    z = (np.asarray(x, dtype=np.float64) - mean) / std\n    h1 = np.tanh(z @ W1.T + b1)",
+     "def forward(P, x):\n    W1, b1, W2, b2, W3, b3, mean, std = unpack(P)\n"
+     "    z = (np.asarray(x, dtype=np.float64) - mean) / std\n    h1 = np.tanh(z @ W1.T) + b1"),
+    ("pressure features in swapped slots",
+     "np.log(WL[:, 2] / pbar),\n                  np.log(WR[:, 2] / pbar)",
+     "np.log(WR[:, 2] / pbar),\n                  np.log(WL[:, 2] / pbar)"),
+    ("sound speed without gamma",
+     "cbar = np.sqrt(gamma * pbar / rbar)", "cbar = np.sqrt(pbar / rbar)"),
+    ("backward through W2 transposed",
+     "d1 = (d2 @ W2) * (1 - h1 * h1)         # upstream", "d1 = (d2 @ W2.T) * (1 - h1 * h1)         # upstream"),
+    ("loss gradient without the factor 2",
+     "dy = 2.0 * (y - t) / n", "dy = (y - t) / n"),
+    ("Adam without the second-moment bias correction",
+     "vh = v / (1 - b2 ** step)", "vh = v"),
+]
+
+
+def _mlp_tests():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_mlp_pins", os.path.join(ROOT, "tests", "test_oracle_mlp.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    tests = [getattr(mod, n) for n in dir(mod) if n.startswith("test_")]
+    return mod, tests
+
+
+@pytest.mark.parametrize("k", range(len(MLP_MUTANTS)))
+def test_every_planted_network_mistake_fails_a_pin(k):
+    import types
+    name, old, new = MLP_MUTANTS[k]
+    src = open(os.path.join(ROOT, "oracle", "mlp.py")).read()
+    assert src.count(old) == 1, f"{name}: expression not found once in oracle/mlp.py"
+    mutant = types.ModuleType("mlp_mutant")
+    exec(compile(src.replace(old, new), "mlp_mutant", "exec"), mutant.__dict__)
+    mod, tests = _mlp_tests()
+    mod.mlp = mutant
+    caught = []
+    for t in tests:
+        try:
+            t()
+        except Exception as e:  # a failed pin
+            caught.append((t.__name__, type(e).__name__))
+    assert caught, f"planted mistake '{name}' passed every network pin"
+
+
+def test_unplanted_network_reference_passes_its_pins_in_the_same_harness():
+    mod, tests = _mlp_tests()
+    for t in tests:
+        t()
