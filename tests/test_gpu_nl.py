@@ -161,17 +161,21 @@ def test_euler_nl_shock_tube_parity(G, order, ratio):
         sim.close()
 
 
-@pytest.mark.parametrize("schedule,block", [(2, 64), (3, 128), (1, 256)])
-def test_euler_nl_network_parity(G, schedule, block):
+@pytest.mark.parametrize("order,schedule,block", [(3, 2, 64), (3, 3, 128), (3, 1, 256), (2, 2, 64),
+                                                  (4, 3, 128), (5, 2, 64)])
+def test_euler_nl_network_parity(G, order, schedule, block):
+    """GRPrecNL on a network of uneven transmissive segments (3 .. 400 cells;
+    at order 5 the reconstruction reads V_{i+-3/2}, the ghost state beyond a
+    segment's end)."""
     net = network_case(40, seed=5, nmax=400)
     S = len(net.n_cells)
-    c = _ocfg(oracle.EULER, 3, oracle.TRANSMISSIVE, 10.0)
+    c = _ocfg(oracle.EULER, order, oracle.TRANSMISSIVE, 10.0)
     v0 = oracle.init_interfaces(c, net.vl, net.vr)
     qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 3)
-    sim = _sim(G, G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+    sim = _sim(G, G.GRPREC_EULER, order, net.n_cells, net.lengths, net.q, net.vl, net.vr,
                G.GRPREC_BC_TRANSMISSIVE, 10.0, schedule=schedule, block=block)
     try:
-        print(f"Euler NL network schedule {schedule} block {block}", flush=True)
+        print(f"Euler NL network order {order} schedule {schedule} block {block}", flush=True)
         steps, _ = sim.run(1e9, 3)
         assert steps == 3
         qg, vg, _, _ = sim.numpy_state()
