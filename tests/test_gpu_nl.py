@@ -225,7 +225,7 @@ def test_nl_parameter_validation(G):
             G.Simulation(G.GRPREC_ADVECTION, 3, [64], [1.0], q, vl, vr, **kw)
 
 
-@pytest.mark.parametrize("guess,order", [(0, 3), (1, 3), (0, 5)])
+@pytest.mark.parametrize("guess,order", [(0, 3), (1, 3), (0, 5), (1, 5), (1, 2), (1, 4)])
 def test_tube_network_parity(G, guess, order):
     """Batched shock tubes (the seeded tube network's first 80 tubes; 40 at
     order 5, whose degree-4 candidates read V_{i-3/2}, V_{i+3/2} and the ghost

@@ -96,6 +96,34 @@ def test_trrs_tube_network_parity(G):
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= T_END, s
 
 
+@pytest.mark.parametrize("order,schedule,block", [(3, 2, 64), (5, 3, 128), (2, 1, 256)])
+def test_trrs_smooth_network_parity(G, order, schedule, block):
+    """The two-rarefaction datum with GRPrec on a network of uneven smooth
+    transmissive segments: every segment after 3 of its own steps equals the
+    single-domain oracle within 1e-10."""
+    from ._cases import network_case
+    net = network_case(30, seed=12, nmax=300)
+    S = len(net.n_cells)
+    c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE, datum=oracle.DATUM_TRRS)
+    v0 = oracle.init_interfaces(c, net.vl, net.vr)
+    qr, vr_, tr, _ = oracle.run_segments(c, net.cell_off, net.dx, net.q, v0, np.zeros(S), 1e9, 3)
+    sim = G.Simulation(G.GRPREC_EULER, order, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                       bc=G.GRPREC_BC_TRANSMISSIVE, datum=G.GRPREC_DATUM_TRRS, schedule=schedule,
+                       block=block)
+    try:
+        print(f"TRRS network order {order} schedule {schedule} block {block}", flush=True)
+        steps, _ = sim.run(1e9, 3)
+        assert steps == 3
+        qg, vg, _, _ = sim.numpy_state()
+        np.testing.assert_allclose(sim.times(), tr, rtol=1e-14)
+    finally:
+        sim.close()
+    for s in range(S):
+        c0, c1 = net.cell_off[s], net.cell_off[s + 1]
+        assert rel_linf(qg[:, c0:c1], qr[:, c0:c1]) <= 1e-10, s
+        assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr_[:, c0 + s:c1 + s + 1]) <= 1e-10, s
+
+
 def test_trrs_rejected_for_advection(G):
     dx, q, vl, vr = I.adv_sin2pi(64)
     with pytest.raises(G.GrprecError):
