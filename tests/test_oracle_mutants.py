@@ -92,6 +92,21 @@ MUTANTS = [
     ("two-rarefaction exponent (g-1)/g",
      "double gm1 = g - 1.0, gp1 = g + 1.0, z = gm1 / (2.0 * g);",
      "double gm1 = g - 1.0, gp1 = g + 1.0, z = gm1 / g;"),
+    ("right ghost cell holding the first cell's average",
+     "GR[vv * (nn + 1) + b] = fac * q[vv * n + n - 1];",
+     "GR[vv * (nn + 1) + b] = fac * q[vv * n + 0];"),
+    ("V_{i+3/2} beyond a transmissive end read as the end interface's value",
+     "vp = (i + 2 <= n) ? vvv[i + 2] : qv[n - 1];",
+     "vp = (i + 2 <= n) ? vvv[i + 2] : vvv[n];"),
+    ("right eigenvector of u - c with H + u c",
+     "double col[3][3] = {{1.0, u - c, H - u * c}, {1.0, u, 0.5 * u * u}, {1.0, u + c, H + u * c}};",
+     "double col[3][3] = {{1.0, u - c, H + u * c}, {1.0, u, 0.5 * u * u}, {1.0, u + c, H + u * c}};"),
+    ("first-step datum from the left limit only",
+     "      QR[vv] = vr[vv * nif + k];",
+     "      QR[vv] = vl[vv * nif + k];"),
+    ("Newton keeps a non-positive iterate's predecessor",
+     "if (pn <= 0.0) pn = 0.5 * p;",
+     "if (pn <= 0.0) pn = p;"),
 ]
 
 

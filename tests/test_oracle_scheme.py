@@ -400,3 +400,69 @@ def test_smax_per_segment_sets_each_segments_step():
     dx = np.array(lengths) / np.array(sizes)
     _, _, t, _ = oracle.run_segments(c, cell_off, dx, q, v, np.zeros(len(sizes)), 1e9, 1)
     np.testing.assert_allclose(t, want, rtol=1e-14)
+
+
+def _mirror(q, v):
+    """x -> -x: cells and interfaces in reverse order, momentum negated."""
+    qm, vm = q[:, ::-1].copy(), v[:, ::-1].copy()
+    qm[1] *= -1.0
+    vm[1] *= -1.0
+    return qm, vm
+
+
+@pytest.mark.parametrize("order,recon", [(3, 0), (5, 0), (5, 1), (4, 1)])
+def test_transmissive_step_is_mirror_symmetric(order, recon):
+    """Both transmissive ends follow one rule (R9, R20: the ghost cell beyond
+    an end holds the end average, also as the V_{i+-3/2} datum GRPrecNL reads
+    at degree 4), so reversing the domain and the sign of the velocity
+    commutes with a step.  The data make the end averages differ from the end
+    interface values, so a rule applied at one end only breaks the symmetry."""
+    n = 37
+    dx = 1.0 / n
+    xf = np.arange(n + 1) * dx
+    xm = 0.5 * (xf[:-1] + xf[1:])
+
+    def prim(x):
+        return 1.0 + 0.3 * x * x + 0.1 * np.sin(7 * x), 0.4 * np.cos(3 * x) - 0.2, 1.0 + 0.5 * x ** 3
+
+    q = I.prim_to_cons(*prim(xm))
+    v = I.prim_to_cons(*prim(xf))
+    c = oracle.cfg(oracle.EULER, order, bc=oracle.TRANSMISSIVE, recon=recon, nl_lambda_c=10.0)
+    qa, va, dta, _, _ = oracle.step(c, dx, q, v, 0.0, 1.0)
+    qmi, vmi = _mirror(q, v)
+    qb, vb, dtb, _, _ = oracle.step(c, dx, qmi, vmi, 0.0, 1.0)
+    qb, vb = _mirror(qb, vb)
+    assert dta == dtb
+    scale = np.abs(q).max()
+    assert np.abs(qa - qb).max() <= 1e-13 * scale
+    assert np.abs(va - vb).max() <= 1e-13 * scale
+    # and the end data matter: the step moved the end cells
+    assert np.abs(qa[:, [0, -1]] - q[:, [0, -1]]).max() > 1e-6
+
+
+@pytest.mark.parametrize("lam", [1.0, -0.7])
+def test_first_step_datum_is_the_upwind_limit_at_a_jump(lam):
+    """R1: the first interface datum is the Riemann solution at x/t = 0
+    between the two one-sided limits; for advection that is the upwind limit
+    (the left one for lambda > 0, the right one for lambda < 0)."""
+    n = 16
+    dx, q, vl, vr = I.adv_square(n)
+    c = oracle.cfg(oracle.ADVECTION, 3, lam=lam)
+    v = oracle.init_interfaces(c, vl, vr)
+    want = vl if lam > 0 else vr
+    assert np.array_equal(v, want)
+    assert not np.array_equal(vl, vr)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_first_step_datum_is_the_upwind_state_in_supersonic_flow(sign):
+    """R1 for the Euler equations: where both one-sided states move faster than
+    their sound speed in one direction, x/t = 0 lies outside the whole wave
+    fan and the datum is the upwind state exactly."""
+    WL = np.array([[1.0, 3.0 * sign, 1.0]])
+    WR = np.array([[0.5, 3.2 * sign, 0.6]])
+    QL, QR = I.prim_to_cons(*WL.T), I.prim_to_cons(*WR.T)
+    c = oracle.cfg(oracle.EULER, 3, bc=oracle.TRANSMISSIVE)
+    v = oracle.init_interfaces(c, QL, QR)
+    want = QL if sign > 0 else QR
+    np.testing.assert_allclose(v, want, rtol=1e-15, atol=0.0)
