@@ -107,6 +107,31 @@ MUTANTS = [
     ("Newton keeps a non-positive iterate's predecessor",
      "if (pn <= 0.0) pn = 0.5 * p;",
      "if (pn <= 0.0) pn = p;"),
+    ("degree-3 least squares counting the right mean twice, not the left",
+     "ls[nls++] = 2; ls[nls++] = 0; ls[nls++] = 3; ls[nls++] = 4;",
+     "ls[nls++] = 2; ls[nls++] = 2; ls[nls++] = 3; ls[nls++] = 4;"),
+    ("degree-2 candidates take the same-side interface value",
+     "{{0, 1, 4}, {1, 2, 3}},", "{{0, 1, 3}, {1, 2, 4}},"),
+    ("characteristic projection with R instead of R^-1",
+     "w[k][j] += Lm[k * 3 + v] * d[v * 7 + j];", "w[k][j] += Rm[k * 3 + v] * d[v * 7 + j];"),
+    ("projection back with R^-1",
+     "coef[v * (m + 1) + r] += Rm[v * 3 + k] * cw[k][r];", "coef[v * (m + 1) + r] += Lm[v * 3 + k] * cw[k][r];"),
+    ("advection interface state taken downwind",
+     "Q0[0] = cf->lambda >= 0.0 ? QL[0] : QR[0];", "Q0[0] = cf->lambda >= 0.0 ? QR[0] : QL[0];"),
+    ("flux time integral with equal weights",
+     "for (int vv = 0; vv < nv; ++vv) Fbar[vv] += s.w[b] * F[vv];",
+     "for (int vv = 0; vv < nv; ++vv) Fbar[vv] += F[vv] / nn;"),
+    ("left end: ghost and cell traces swapped",
+     "      tl = GL;\n      tr = TL;", "      tl = TL;\n      tr = GL;"),
+    ("periodic interface between the wrong cells",
+     "int cl = (k - 1 + n) % n, cr = k % n;", "int cl = k % n, cr = (k - 1 + n) % n;"),
+    ("indicator quadrature on the shifted cell",
+     "double xi = g[k] - 0.5; /* x = x_i + xi dx */", "double xi = g[k]; /* x = x_i + xi dx */"),
+    ("side candidates' linear weight 2",
+     "#define ORC_NL_LAMBDA_SIDE 1.0", "#define ORC_NL_LAMBDA_SIDE 2.0"),
+    ("predictor data evaluated at g instead of g - 1/2",
+     "w[vv * nn + a] = orc_poly(m, coef + vv * (m + 1), s.g[a] - 0.5);",
+     "w[vv * nn + a] = orc_poly(m, coef + vv * (m + 1), s.g[a]);"),
 ]
 
 
