@@ -132,6 +132,24 @@ MUTANTS = [
     ("predictor data evaluated at g instead of g - 1/2",
      "w[vv * nn + a] = orc_poly(m, coef + vv * (m + 1), s.g[a] - 0.5);",
      "w[vv * nn + a] = orc_poly(m, coef + vv * (m + 1), s.g[a]);"),
+    ("ghost states without the source's decay",
+     "const double fac = kap == 0.0 ? 1.0 : (b < nn ? s.Kinv_l0[b] : gend);",
+     "const double fac = 1.0;"),
+    ("ghost end-of-step factor from the t = 0 basis values",
+     "for (int b = 0; b < nn; ++b) gend += s.l1[b] * s.Kinv_l0[b];",
+     "for (int b = 0; b < nn; ++b) gend += s.l0[b] * s.Kinv_l0[b];"),
+    ("source integral without the time weights",
+     "acc += s.w[a] * s.w[b] * (-kap * qh[(vv * nn + a) * nn + b]);",
+     "acc += s.w[a] * (-kap * qh[(vv * nn + a) * nn + b]);"),
+    ("two-rarefaction star velocity with the sound-speed changes swapped",
+     "double u = 0.5 * (ul + ur) + ((csr - cr) - (csl - cl)) / gm1;",
+     "double u = 0.5 * (ul + ur) + ((csl - cl) - (csr - cr)) / gm1;"),
+    ("two-rarefaction left fan tested against u* + c*",
+     "    } else if (u - csl < 0.0) {", "    } else if (u + csl < 0.0) {"),
+    ("time step without the CFL number",
+     "double d = cfl * dx / S;\n  if (d >= t_end - t) {", "double d = dx / S;\n  if (d >= t_end - t) {"),
+    ("S_max dropping a NaN cell",
+     "if (isnan(si) || isnan(s)) {", "if (isnan(s)) {"),
 ]
 
 
