@@ -155,6 +155,17 @@ MUTANTS = [
      "double d = cfl * dx / S;\n  if (d >= t_end - t) {", "double d = dx / S;\n  if (d >= t_end - t) {"),
     ("S_max dropping a NaN cell",
      "if (isnan(si) || isnan(s)) {", "if (isnan(s)) {"),
+    ("primitive pressure without the kinetic half",
+     "W[2] = (g - 1.0) * (Q[2] - 0.5 * Q[1] * W[1]);", "W[2] = (g - 1.0) * (Q[2] - Q[1] * W[1]);"),
+    ("conserved energy with p (g - 1)",
+     "Q[2] = W[2] / (g - 1.0) + 0.5 * W[0] * W[1] * W[1];", "Q[2] = W[2] * (g - 1.0) + 0.5 * W[0] * W[1] * W[1];"),
+    ("Legendre recurrence with k + 1 in the second term",
+     "double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;",
+     "double pk = ((2.0 * k - 1.0) * x * p1 - (k + 1.0) * p0) / k;"),
+    ("Lagrange derivative without the 1/(g_k - g_j) factor",
+     "double term = 1.0 / (g[k] - g[j]);", "double term = 1.0;"),
+    ("Lagrange basis with the node order reversed in the denominator",
+     "if (j != k) v *= (x - g[j]) / (g[k] - g[j]);", "if (j != k) v *= (x - g[j]) / (g[j] - g[k]);"),
 ]
 
 
