@@ -186,3 +186,33 @@ def test_tube_network_full_size(G, datum):
         qr, vr, _, kr, _ = oracle.run(c, net.dx[s], net.q[:, c0:c1], v, 0.0, 1e9, steps)
         assert rel_linf(qg[:, c0:c1], qr) <= 1e-10, s
         assert rel_linf(vg[:, c0 + s:c1 + s + 1], vr) <= 1e-10, s
+
+
+def test_network_full_size_long_run_stays_physical(G):
+    """The 10^4-segment network in its benchmark configuration (autotuned
+    schedule, graph-captured steps) for 5,000 steps: no latched error, every
+    state finite with positive density and pressure, every segment's time
+    advanced by about 5,000 of its own steps C dx / S_max (times finite and
+    within 20 % of that), and the states still the smooth flow they started
+    as (density within the initial range widened by 1 %)."""
+    net = I.network(n_seg=10000, seed=I.SEED_NETWORK)
+    sim = G.Simulation(G.GRPREC_EULER, 3, net.n_cells, net.lengths, net.q, net.vl, net.vr,
+                       bc=G.GRPREC_BC_TRANSMISSIVE, schedule=G.GRPREC_SCHED_AUTO)
+    try:
+        print("full network, 5000 steps", flush=True)
+        steps, _ = sim.run(1e9, 5000)
+        assert steps == 5000
+        q, v, _, k = sim.numpy_state()
+        times = np.asarray(sim.times())
+    finally:
+        sim.close()
+    assert k == 5000
+    assert np.isfinite(q).all() and np.isfinite(v).all()
+    rho, mom, E = q
+    p = 0.4 * (E - 0.5 * mom * mom / rho)
+    assert (rho > 0).all() and (p > 0).all()
+    assert np.isfinite(times).all() and (times > 0).all()
+    # a segment's step is C dx / S_max with S_max near |u| + c = 0.5 + sqrt(1.4)
+    np.testing.assert_allclose(times, 5000 * 0.9 * net.dx / (0.5 + np.sqrt(1.4)), rtol=0.2)
+    r0 = net.q[0]
+    assert rho.min() > r0.min() - 0.01 * abs(r0.min()) and rho.max() < r0.max() + 0.01 * r0.max()
