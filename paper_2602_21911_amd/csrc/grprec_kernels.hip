@@ -84,6 +84,23 @@ __device__ __forceinline__ void adv_coeffs(double qm, double qc, double qp, doub
   }
 }
 
+// Lane shifts of the advection step: lane l receives lane l-1 (adv_prev) or
+// l+1 (adv_next); the lane without a source (0, resp. 63) receives 0.  Only
+// lanes that no updated lane reads are left without a source, and the result
+// goes straight to a new register (no copy of the old value first).
+__device__ __forceinline__ double adv_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double adv_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Runs per wave per block chunk.  Measured at 2^25 cells over 1, 2, 3, 4, 8,
 // 12 and 16: the memory-bound GRPrec kernels run best with 2 (more blocks in
 // flight), the arithmetic-bound GRPrecNL kernels with 8.
@@ -107,7 +124,7 @@ constexpr int adv_run() {
 // translation; being linear, its flux mean, end-of-step datum and space-time
 // mean are fixed linear combinations of the cell mean and the coefficients,
 // computed once per step by adv_source_prep into a.src.
-template <int M, bool NL, bool SRC>
+template <int M, bool NL, bool SRC, bool POS>
 __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   Ctl *ctl = a.ctl;
   const int slot = a.slot, s1 = (slot + 1) % 3, s2 = (slot + 2) % 3;
@@ -134,7 +151,7 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
   bool done;
   domain_dt(a.cfl, dx, fabs(a.lambda), t, t_end, dt, t_new, done);
   const double cn = a.lambda * dt / dx;  // signed Courant number
-  const bool pos = a.lambda > 0.0;
+  constexpr bool pos = POS;  // lambda > 0: the upwind side is the left
   // per-step constants: mean of each basis function over the swept interval
   // and its value at the foot of the characteristic
   double Kin[4], Pin[4], Sin[4] = {0.0, 0.0, 0.0, 0.0};
@@ -223,11 +240,11 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
       qk = i <= n + 1 ? Q(i) : 0.0;
       vk = VG(i);
     }
-    double qm = wave_prev(qk), qp = wave_next(qk), vp = wave_next(vk);
+    double qm = adv_prev(qk), qp = adv_next(qk), vp = adv_next(vk);
     double vm = 0.0, vpp = 0.0;
     if constexpr (NL && M == 4) {
-      vm = wave_prev(vk);
-      vpp = wave_next(wave_next(vk));
+      vm = adv_prev(vk);
+      vpp = adv_next(adv_next(vk));
     }
     // the lane's flux mean over the swept interval and its datum; at i = -1
     // and i = n the upwind neighbour is the periodic image or the ghost cell
@@ -270,8 +287,8 @@ __global__ __launch_bounds__(256) void adv_step(AdvArgs<M> a) {
         if constexpr (SRC) src_s += ac[j] * Sin[j];
       }
     }
-    const double mean_u = pos ? wave_prev(mean_s) : wave_next(mean_s);
-    const double pt_u = pos ? wave_prev(pt_s) : wave_next(pt_s);
+    const double mean_u = pos ? adv_prev(mean_s) : adv_next(mean_s);
+    const double pt_u = pos ? adv_prev(pt_s) : adv_next(pt_s);
     if (!own || i < 0 || i >= n) continue;
     if (done) {
       qout[i] = qin[i];
@@ -484,17 +501,23 @@ hipError_t launch_adv(const AdvArgs<M> &a, int grid, bool nl, hipStream_t st) {
                           : 4LL * adv_passes<false>() * adv_run<M, false>();
   const long long per = ((a.n + ch - 1) / ch + 7) / 8;
   const int g = (int)(8 * per < (1 << 20) ? 8 * per : (1 << 20));
+  const bool pos = a.lambda > 0.0;
   if (a.src) {
     // the source's per-step maps first (stream order makes them visible)
     hipLaunchKernelGGL((adv_source_prep<M>), dim3(1), dim3(64), 0, st, a);
-    if (nl)
-      hipLaunchKernelGGL((adv_step<M, true, true>), dim3(g), dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((adv_step<M, false, true>), dim3(g), dim3(256), 0, st, a);
+    if (nl) {
+      if (pos) hipLaunchKernelGGL((adv_step<M, true, true, true>), dim3(g), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((adv_step<M, true, true, false>), dim3(g), dim3(256), 0, st, a);
+    } else {
+      if (pos) hipLaunchKernelGGL((adv_step<M, false, true, true>), dim3(g), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((adv_step<M, false, true, false>), dim3(g), dim3(256), 0, st, a);
+    }
   } else if (nl) {
-    hipLaunchKernelGGL((adv_step<M, true, false>), dim3(g), dim3(256), 0, st, a);
+    if (pos) hipLaunchKernelGGL((adv_step<M, true, false, true>), dim3(g), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((adv_step<M, true, false, false>), dim3(g), dim3(256), 0, st, a);
   } else {
-    hipLaunchKernelGGL((adv_step<M, false, false>), dim3(g), dim3(256), 0, st, a);
+    if (pos) hipLaunchKernelGGL((adv_step<M, false, false, true>), dim3(g), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((adv_step<M, false, false, false>), dim3(g), dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
